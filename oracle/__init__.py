@@ -1,0 +1,329 @@
+"""FP64 CPU oracle for the X-GS Perceiver hot path.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the package smoke check and the
+bench's CPU-baseline leg are the only callers.  Nothing here is imported by the
+HIP path, and nothing here imports it.  The compiled part (``oracle.c``) covers
+projection, binning, compositing and their gradients and the VQ distances; this
+module wraps it and adds the two steps that are plain array arithmetic in numpy
+(grid-sampled targets and the EMA codebook update).
+
+Every function works in float64.  Inputs that the product stores in binary32
+are widened exactly before use.
+
+Parity pins: see ``tests/test_oracle_*.py`` (closed forms, invariants, brute
+force, finite differences, library cross-checks).  Every function here is
+pinned; none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+TILE = 16
+ALPHA_MIN = 1.0 / 255.0
+ALPHA_MAX = 0.99
+T_STOP = 1e-4
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc (IEEE double, no
+    fast-math).  OpenMP parallelises only the row loop of the VQ distances."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               "-fno-fast-math", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        for name in ("orc_project", "orc_composite_fwd", "orc_composite_list", "orc_composite_bwd",
+                     "orc_project_bwd", "orc_vq_assign", "orc_grid_info"):
+            getattr(_lib, name).restype = ctypes.c_int
+        _lib.orc_bin.restype = ctypes.c_int64
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def cam_array(cam) -> np.ndarray:
+    """Camera -> the double[26] layout documented in oracle.c."""
+    v = np.asarray(cam.viewmat, dtype=np.float64).reshape(16)
+    return np.concatenate([[cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near,
+                            cam.stride, cam.off_y, cam.off_x], v]).astype(np.float64)
+
+
+def grid_info(cam):
+    out = np.zeros(4, dtype=np.int32)
+    lib().orc_grid_info(_p(cam_array(cam)), _p(out))
+    hs, ws, ty, tx = (int(v) for v in out)
+    return hs, ws, ty, tx
+
+
+@dataclass
+class Projection:
+    mean2d: np.ndarray   # [n,2]
+    conic: np.ndarray    # [n,3]  A, B, C of A dx^2 + 2B dx dy + C dy^2
+    depth: np.ndarray    # [n]    camera z
+    cov2d: np.ndarray    # [n,3]  a, b, c of Sigma' (with dilation)
+    ext: np.ndarray      # [n,2]  half-widths of the opacity-aware box
+    rect: np.ndarray     # [n,4]  int32 tiles [x0, y0, x1, y1) exclusive upper
+    touched: np.ndarray  # [n]    int64
+    visible: np.ndarray  # [n]    int32
+
+
+def project(scene, cam) -> Projection:
+    """EWA projection of every Gaussian (App. A: Sigma = R S S^T R^T,
+    Sigma' = J W Sigma W^T J^T), plus the opacity-aware tile rectangle."""
+    n = scene.n
+    out = Projection(np.zeros((n, 2)), np.zeros((n, 3)), np.zeros(n), np.zeros((n, 3)),
+                     np.zeros((n, 2)), np.zeros((n, 4), np.int32), np.zeros(n, np.int64),
+                     np.zeros(n, np.int32))
+    lib().orc_project(ctypes.c_int64(n), _p(_f64(scene.means)), _p(_f64(scene.log_scales)),
+                      _p(_f64(scene.quats)), _p(_f64(scene.opacity)), _p(cam_array(cam)),
+                      _p(out.mean2d), _p(out.conic), _p(out.depth), _p(out.cov2d), _p(out.ext),
+                      _p(out.rect), _p(out.touched), _p(out.visible))
+    return out
+
+
+def depth_bits(depth) -> np.ndarray:
+    """The sort key's depth part: the binary32 value of camera z, as bits."""
+    return np.ascontiguousarray(np.asarray(depth, dtype=np.float32).view(np.uint32))
+
+
+def bin_instances(rect, dbits, tiles_x: int, tiles_y: int):
+    """(tile, depth-bits, index)-sorted instance list and per-tile ranges."""
+    rect = np.ascontiguousarray(rect, dtype=np.int32)
+    dbits = np.ascontiguousarray(dbits, dtype=np.uint32)
+    n = rect.shape[0]
+    m = int(((rect[:, 2] - rect[:, 0]).astype(np.int64) * (rect[:, 3] - rect[:, 1])).sum())
+    keys = np.zeros(max(m, 1), np.uint64)
+    vals = np.zeros(max(m, 1), np.uint32)
+    ranges = np.zeros(2 * tiles_x * tiles_y, np.uint32)
+    got = lib().orc_bin(ctypes.c_int64(n), _p(rect), _p(dbits), ctypes.c_int32(tiles_x),
+                        ctypes.c_int32(tiles_y), ctypes.c_int64(m), _p(keys), _p(vals), _p(ranges))
+    assert got == m
+    return keys[:m], vals[:m], ranges.reshape(-1, 2)
+
+
+def channels(scene, depth) -> np.ndarray:
+    """Per-Gaussian channel rows [RGB, depth, semantic...] (Sec. 3.1 and
+    App. B: the depth and feature maps substitute d_i and f_i for c_i)."""
+    return np.ascontiguousarray(np.concatenate(
+        [_f64(scene.colors), _f64(depth)[:, None], _f64(scene.features)], axis=1))
+
+
+@dataclass
+class Render:
+    proj: Projection
+    keys: np.ndarray
+    order: np.ndarray
+    ranges: np.ndarray
+    out: np.ndarray       # [C, Hs, Ws]
+    final_T: np.ndarray   # [Hs, Ws]
+    n_last: np.ndarray    # [Hs, Ws]
+    amb: np.ndarray       # [3, Hs, Ws] skip, stop, depth-gap ambiguity measures
+    chan: np.ndarray
+
+
+def composite_fwd(proj: Projection, opacity, chan, order, ranges, cam, tile_mask=None,
+                  depth=None):
+    hs, ws, ty, tx = grid_info(cam)
+    C = chan.shape[1]
+    out = np.zeros((C, hs, ws))
+    fT = np.ones((hs, ws))
+    nl = np.zeros((hs, ws), np.int64)
+    amb = np.full((3, hs, ws), np.inf)
+    tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, dtype=np.uint8)
+    lib().orc_composite_fwd(ctypes.c_int64(len(opacity)), _p(_f64(proj.mean2d)),
+                            _p(_f64(proj.conic)), _p(_f64(opacity)), _p(_f64(chan)),
+                            _p(_f64(proj.depth if depth is None else depth)), ctypes.c_int32(C),
+                            _p(np.ascontiguousarray(order, np.uint32)),
+                            _p(np.ascontiguousarray(ranges, np.uint32)), _p(cam_array(cam)),
+                            _p(tm), _p(out), _p(fT), _p(nl), _p(amb))
+    return out, fT, nl, amb
+
+
+def render(scene, cam, tile_mask=None) -> Render:
+    """Project -> bin -> composite, all in the oracle (FP64 arithmetic; only the
+    depth sort key is binary32, as the reading of the sort key requires)."""
+    hs, ws, ty, tx = grid_info(cam)
+    pr = project(scene, cam)
+    keys, order, ranges = bin_instances(pr.rect, depth_bits(pr.depth), tx, ty)
+    chan = channels(scene, pr.depth)
+    out, fT, nl, amb = composite_fwd(pr, scene.opacity, chan, order, ranges, cam, tile_mask)
+    return Render(pr, keys, order, ranges, out, fT, nl, amb, chan)
+
+
+def composite_list(proj: Projection, opacity, chan, order, cam):
+    """No tiles: every pixel walks the same global list."""
+    hs, ws, _, _ = grid_info(cam)
+    C = chan.shape[1]
+    out = np.zeros((C, hs, ws))
+    fT = np.ones((hs, ws))
+    order = np.ascontiguousarray(order, np.uint32)
+    lib().orc_composite_list(_p(_f64(proj.mean2d)), _p(_f64(proj.conic)), _p(_f64(opacity)),
+                             _p(_f64(chan)), ctypes.c_int32(C), _p(order),
+                             ctypes.c_int64(len(order)), _p(cam_array(cam)), _p(out), _p(fT))
+    return out, fT
+
+
+@dataclass
+class Grads:
+    means: np.ndarray
+    log_scales: np.ndarray
+    quats: np.ndarray
+    opacity: np.ndarray
+    colors: np.ndarray
+    features: np.ndarray
+    mean2d: np.ndarray
+    conic: np.ndarray
+
+
+def render_grad(scene, cam, g, r: Render | None = None, tile_mask=None) -> Grads:
+    """Analytic FP64 gradient of L = sum g * out for every parameter group."""
+    if r is None:
+        r = render(scene, cam, tile_mask)
+    n = scene.n
+    C = r.chan.shape[1]
+    d_m2 = np.zeros((n, 2)); d_co = np.zeros((n, 3)); d_op = np.zeros(n); d_ch = np.zeros((n, C))
+    tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, dtype=np.uint8)
+    lib().orc_composite_bwd(ctypes.c_int64(n), _p(_f64(r.proj.mean2d)), _p(_f64(r.proj.conic)),
+                            _p(_f64(scene.opacity)), _p(r.chan), ctypes.c_int32(C),
+                            _p(np.ascontiguousarray(r.order, np.uint32)),
+                            _p(np.ascontiguousarray(r.ranges, np.uint32)), _p(cam_array(cam)),
+                            _p(_f64(g)), _p(tm), _p(d_m2), _p(d_co), _p(d_op), _p(d_ch))
+    d_means = np.zeros((n, 3)); d_ls = np.zeros((n, 3)); d_q = np.zeros((n, 4))
+    lib().orc_project_bwd(ctypes.c_int64(n), _p(_f64(scene.means)), _p(_f64(scene.log_scales)),
+                          _p(_f64(scene.quats)), _p(_f64(scene.opacity)), _p(cam_array(cam)),
+                          _p(d_m2), _p(d_co), _p(np.ascontiguousarray(d_ch[:, 3])), _p(d_means),
+                          _p(d_ls), _p(d_q))
+    return Grads(d_means, d_ls, d_q, d_op, d_ch[:, :3].copy(), d_ch[:, 4:].copy(), d_m2, d_co)
+
+
+def project_bwd(scene, cam, d_mean2d, d_conic, d_depth):
+    n = scene.n
+    d_means = np.zeros((n, 3)); d_ls = np.zeros((n, 3)); d_q = np.zeros((n, 4))
+    lib().orc_project_bwd(ctypes.c_int64(n), _p(_f64(scene.means)), _p(_f64(scene.log_scales)),
+                          _p(_f64(scene.quats)), _p(_f64(scene.opacity)), _p(cam_array(cam)),
+                          _p(_f64(d_mean2d)), _p(_f64(d_conic)), _p(_f64(d_depth)), _p(d_means),
+                          _p(d_ls), _p(d_q))
+    return d_means, d_ls, d_q
+
+
+def loss(out, g) -> float:
+    return float((np.asarray(out, np.float64) * np.asarray(g, np.float64)).sum())
+
+
+# --------------------------------------------------------------- grid sample
+BILINEAR = 0
+NEAREST = 1
+
+
+def grid_sample(P, H: int, W: int, stride: int = 1, off_y: int = 0, off_x: int = 0,
+                mode: int = BILINEAR):
+    """Targets on the sampled grid (App. D, Eq. (sampled_loc), Eq. (target_continuous)).
+
+    (u, v) = (off_y + m s, off_x + n s); u~ = u (Hf-1)/max(H-1,1), v~ likewise.
+    NEAREST takes P at the rounded (u~, v~) (round half to even, done exactly in
+    integers); BILINEAR interpolates P at (u~, v~).  V = 1 inside the image and
+    0 (with G = 0) where u >= H or v >= W.
+    """
+    P = _f64(P)
+    D, Hf, Wf = P.shape
+    Hs, Ws = -(-H // stride), -(-W // stride)
+    u = off_y + np.arange(Hs, dtype=np.int64) * stride
+    v = off_x + np.arange(Ws, dtype=np.int64) * stride
+    by, bx = max(H - 1, 1), max(W - 1, 1)
+    ay, ax = u * (Hf - 1), v * (Wf - 1)
+    qy, ry = np.divmod(ay, by)
+    qx, rx = np.divmod(ax, bx)
+    valid = (u[:, None] < H) & (v[None, :] < W)
+    if mode == NEAREST:
+        iy = qy + ((2 * ry > by) | ((2 * ry == by) & (qy % 2 == 1)))
+        ix = qx + ((2 * rx > bx) | ((2 * rx == bx) & (qx % 2 == 1)))
+        iy = np.minimum(iy, Hf - 1); ix = np.minimum(ix, Wf - 1)
+        G = P[:, iy[:, None], ix[None, :]]
+    else:
+        y0 = np.minimum(qy, Hf - 1); x0 = np.minimum(qx, Wf - 1)
+        y1 = np.minimum(y0 + 1, Hf - 1); x1 = np.minimum(x0 + 1, Wf - 1)
+        wy = (ry / by)[:, None]; wx = (rx / bx)[None, :]
+        G = ((1 - wy) * (1 - wx) * P[:, y0[:, None], x0[None, :]]
+             + (1 - wy) * wx * P[:, y0[:, None], x1[None, :]]
+             + wy * (1 - wx) * P[:, y1[:, None], x0[None, :]]
+             + wy * wx * P[:, y1[:, None], x1[None, :]])
+    G = np.where(valid[None], G, 0.0)
+    return G, valid.astype(np.uint8)
+
+
+# ------------------------------------------------------------------------ VQ
+def vq_assign(X, E):
+    """a_n = argmin_l ||x_n - E_l||^2 in FP64 (Sec. 3.2.2), lowest index on ties.
+    Returns (idx int32, best squared distance, second-best squared distance)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    E = np.ascontiguousarray(E, dtype=np.float32)
+    N, D = X.shape
+    K = E.shape[0]
+    idx = np.zeros(N, np.int32); d1 = np.zeros(N); d2 = np.zeros(N)
+    lib().orc_vq_assign(ctypes.c_int64(N), ctypes.c_int32(D), _p(X), ctypes.c_int32(K), _p(E),
+                        _p(idx), _p(d1), _p(d2))
+    return idx, d1, d2
+
+
+PAPER = 0
+LAPLACE = 1
+
+
+def ema_init(E):
+    """Reading: the EMA state starts at N = 1, M = E for every codeword."""
+    E = _f64(E)
+    return np.ones(E.shape[0]), E.copy()
+
+
+def ema_update(X, idx, N_ema, M_ema, decay: float, eps: float, mode: int = LAPLACE):
+    """One step of Eq. (ema_update).
+
+    c_l = #{n : a_n = l},  s_l = sum_{a_n = l} x_n,
+    N <- lambda N + (1-lambda) c,  M <- lambda M + (1-lambda) s,
+    PAPER:   E_l = M_l / (N_l + eps)
+    LAPLACE: E_l = M_l / Ntilde_l, Ntilde_l = (N_l + eps) / (n + K eps) * n, n = sum_l N_l.
+    Returns (N, M, E, counts, sums) in FP64."""
+    X = _f64(X)
+    idx = np.asarray(idx, dtype=np.int64)
+    K, D = M_ema.shape
+    counts = np.zeros(K)
+    sums = np.zeros((K, D))
+    for n in range(X.shape[0]):
+        counts[idx[n]] += 1.0
+        sums[idx[n]] += X[n]
+    N_new = decay * _f64(N_ema) + (1.0 - decay) * counts
+    M_new = decay * _f64(M_ema) + (1.0 - decay) * sums
+    if mode == PAPER:
+        E_new = M_new / (N_new + eps)[:, None]
+    else:
+        tot = N_new.sum()
+        nt = (N_new + eps) / (tot + K * eps) * tot
+        E_new = M_new / nt[:, None]
+    return N_new, M_new, E_new, counts, sums
