@@ -1,0 +1,261 @@
+"""Benchmark of the X-GS Perceiver hot path on one MI355X.
+
+One step = one pass of every hot-path row over one batch of synthetic input:
+  a1-a4  project -> tile sort -> render forward -> render backward of a
+         1,000,000-Gaussian synthetic room at 1200x680 with 3 + 1 + 32
+         channels, at the next pose of a random-walk trajectory;
+  a5     bilinear grid sampling of a 512 x 30 x 40 feature map to 640 x 480;
+  a6-a7  BF16-MFMA VQ assignment (top-4 + FP32 rescore) of 816,000 x 768
+         features against 4,096 codewords, then one EMA update.
+The headline value is fwd+bwd ms/frame (a1-a4, HIP events on the launch
+stream, mean over the timed steps).  Everything is resident in HBM before the
+timed region; nothing is skipped inside it.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd ms/frame at 1M Gaussians 1200x680 32-ch"
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2603_09632_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, src: list[str], launches_bytes_alg: float):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    or None if it is missing or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    e = d.get(kernel)
+    if not e or e.get("source_sha") != source_sha(*src):
+        return None
+    return float(e["bytes_per_launch"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration for profiles)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2603_09632_amd as xgs
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    # ---------------------------------------------------------------- inputs
+    log("generating the 1M-Gaussian room")
+    scene = synth.room_scene(1_000_000, seed=2, c_sem=32)
+    g = xgs.Gaussians(t(scene.means), t(scene.log_scales), t(scene.quats), t(scene.opacity), t(scene.colors),
+                      t(scene.features))
+    poses = synth.room_trajectory(100, seed=10)
+    nframes = args.warmup + args.steps
+    cams = [xgs.camera_from(synth.room_camera(1200, 680, 600.0, poses[(5 + k) % len(poses)]))
+            for k in range(nframes)]
+    hs, ws, ty, tx = xgs.grid_dims(cams[0])
+    C = 4 + scene.c_sem
+    p = xgs.Projected.alloc(g.n, dev)
+    # capacity: the largest instance count over the poses, plus headroom
+    mmax = 0
+    for c in cams:
+        xgs.xgs_project(g, c, out=p)
+        mmax = max(mmax, int(p.tiles_touched.to(torch.int64).sum().item()))
+    b = xgs.alloc_binning(g.n, int(mmax * 1.25) + 1024, cams[0], dev)
+    out = torch.empty((C, hs, ws), device=dev)
+    fT = torch.empty((hs, ws), device=dev)
+    nl = torch.empty((hs, ws), dtype=torch.int32, device=dev)
+    d_out = t(synth.upstream_grad(C, hs, ws, seed=1))
+    grads = xgs.Gaussians.empty_like(g)
+    bwd_ws = torch.empty(int(xgs.lib.xgs_render_bwd_workspace(g.n)), dtype=torch.uint8, device=dev)
+
+    log("generating the feature map and the VQ features")
+    P = t(synth.feature_map(512, 30, 40, seed=5))
+    G = torch.empty((512, 480, 640), device=dev)
+    V = torch.empty((480, 640), dtype=torch.uint8, device=dev)
+    Xh = synth.vq_mixture(816_000, 768, 256, seed=30)
+    Eh = synth.vq_codebook(4096, 768, 256, seed=31, centre_seed=30)
+    X = t(Xh)
+    E0 = t(Eh)
+    E = E0.clone()
+    Eb, en = xgs.xgs_vq_prepare(E)
+    idx = torch.empty(X.shape[0], dtype=torch.int32, device=dev)
+    dist = torch.empty(X.shape[0], device=dev)
+    Nema = torch.ones(4096, device=dev)
+    Mema = E0.clone()
+    counts = torch.empty(4096, device=dev)
+    ema_ws = torch.empty(int(xgs.lib.xgs_vq_ema_workspace(X.shape[0], 768, 4096)), dtype=torch.uint8, device=dev)
+    if args.calib_copy:
+        src = torch.empty(256 * 1024 * 1024, device=dev)
+        dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+
+    names = ["project", "tile_sort", "render_fwd", "render_bwd", "grid_sample", "vq_assign", "vq_ema"]
+    stream = torch.cuda.current_stream()
+
+    def step(k, evs):
+        c = cams[k]
+        evs[0].record(stream)
+        xgs.xgs_project(g, c, out=p)
+        evs[1].record(stream)
+        xgs.xgs_tile_sort(p, c, g.n, b)
+        evs[2].record(stream)
+        xgs.xgs_render_fwd(g, p, b, c, out=out, final_T=fT, n_last=nl)
+        evs[3].record(stream)
+        xgs.xgs_render_bwd(g, p, b, c, d_out, fT, nl, grads=grads, workspace=bwd_ws)
+        evs[4].record(stream)
+        xgs.xgs_grid_sample(P, 480, 640, G=G, V=V)
+        evs[5].record(stream)
+        xgs.xgs_vq_assign(X, E, Eb, en, xgs.VQ_BF16_RESCORE4, idx=idx, dist=dist)
+        evs[6].record(stream)
+        xgs.xgs_vq_ema_update(X, idx, Nema, Mema, E, Eb, en, 0.99, 1e-5, xgs.EMA_LAPLACE, counts=counts,
+                              workspace=ema_ws)
+        evs[7].record(stream)
+
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    log(f"warmup {args.warmup} steps")
+    for k in range(args.warmup):
+        step(k, mk())
+    torch.cuda.synchronize()
+    if int(b.status.item()) != 0:
+        raise RuntimeError("binning capacity exceeded during warmup")
+    log(f"timing {args.steps} steps")
+    evs_all = [mk() for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k, evs_all[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if int(b.status.item()) != 0:
+        raise RuntimeError("binning capacity exceeded in the timed region")
+    per = {n: [] for n in names}
+    for evs in evs_all:
+        for i, n in enumerate(names):
+            per[n].append(evs[i].elapsed_time(evs[i + 1]))
+    if args.calib_copy:
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    ms = {n: float(np.mean(v)) for n, v in per.items()}
+    frame = [sum(per[n][k] for n in names[:4]) for k in range(args.steps)]
+    value = float(np.mean(frame))
+    m_inst = int(b.num_instances.item())
+
+    # ------------------------------------------------------------ rooflines
+    N, D, K = X.shape[0], 768, 4096
+    vq_flop = 2.0 * N * K * D
+    vq_tflops = vq_flop / (ms["vq_assign"] * 1e-3) / 1e12
+    vq_gbs = N * D * 4 / (ms["vq_assign"] * 1e-3) / 1e9
+    grid_bytes = 512 * 480 * 640 * 4 + 480 * 640 + 512 * 30 * 40 * 4
+    grid_gbs = grid_bytes / (ms["grid_sample"] * 1e-3) / 1e9
+    # compositing forward: per instance val + splat + rgb + features; per pixel outputs
+    fwd_bytes = m_inst * (4 + 32 + 12 + 4 * scene.c_sem) + hs * ws * 4 * (C + 2)
+    fwd_gbs = fwd_bytes / (ms["render_fwd"] * 1e-3) / 1e9
+    timed = {"render_bwd": ms["render_bwd"], "vq_assign": ms["vq_assign"], "render_fwd": ms["render_fwd"]}
+    dominant = max(timed, key=timed.get)
+    if dominant == "vq_assign":
+        roof = {"kernel": "vq_bf16_kernel", "bound": "mfma", "achieved": round(vq_tflops, 2),
+                "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(vq_tflops / BF16_PEAK_TFLOPS, 4),
+                "traffic": traffic_for("vq_bf16_kernel", ["vq.hip"], vq_flop),
+                "algorithmic": f"2*N*K*D = {vq_flop:.3e} flop per launch (N=816000, K=4096, D=768)"}
+    else:
+        bwd_bytes = fwd_bytes + g.n * 4 * (3 + 3 + 4 + 1 + 3 + scene.c_sem) * 2
+        a = bwd_bytes / (ms[dominant] * 1e-3) / 1e9
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic": f"{bwd_bytes:.3e} bytes per launch"}
+
+    result = {
+        "metric": METRIC, "value": round(value, 4), "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded room scene, trajectory, VFM-like maps, mixture VQ features)",
+        "config": {"workload": "1M-Gaussian synthetic room, 1200x680, 3+1+32 channels, fwd+bwd per frame; "
+                               "grid_sample 512x30x40 -> 640x480; VQ 816000x768 vs K=4096 (bf16+rescore) + EMA",
+                   "gaussians": g.n, "width": 1200, "height": 680, "c_sem": scene.c_sem,
+                   "instances_last_frame": m_inst},
+        "ms": {k: round(v, 4) for k, v in ms.items()},
+        "frame_ms_median": round(float(np.median(frame)), 4),
+        "vq_assign_GBps": round(vq_gbs, 1), "vq_assign_TFLOPs": round(vq_tflops, 1),
+        "grid_sample_GBps": round(grid_gbs, 1), "render_fwd_alg_GBps": round(fwd_gbs, 1),
+        "roofline": roof,
+    }
+
+    # ------------------------------------------------------------ CPU baseline
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(scene, synth)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(scene, synth):
+    """The FP64 oracle (single-threaded C) on one frame of the same workload:
+    projection and binning of all 1M Gaussians, compositing forward + backward
+    on every 3rd row of tiles; the compositing time is scaled by the tile
+    fraction to a whole frame."""
+    import oracle
+
+    cam = synth.room_camera(1200, 680, 600.0, synth.room_trajectory(100, seed=10)[5])
+    hs, ws, ty, tx = oracle.grid_info(cam)
+    mask = np.zeros((ty, tx), np.uint8)
+    mask[::3] = 1
+    frac = mask.mean()
+    g = synth.upstream_grad(4 + scene.c_sem, hs, ws, seed=1).astype(np.float64)
+    t0 = time.perf_counter()
+    pr = oracle.project(scene, cam)
+    keys, order, ranges = oracle.bin_instances(pr.rect, oracle.depth_bits(pr.depth), tx, ty)
+    t1 = time.perf_counter()
+    chan = oracle.channels(scene, pr.depth)
+    out, fT, nl, amb = oracle.composite_fwd(pr, scene.opacity, chan, order, ranges, cam, mask.ravel())
+    r = oracle.Render(pr, keys, order, ranges, out, fT, nl, amb, chan)
+    oracle.render_grad(scene, cam, g, r, tile_mask=mask.ravel())
+    t2 = time.perf_counter()
+    # render_grad includes the projection backward of all Gaussians once
+    frame_s = (t1 - t0) + (t2 - t1) / frac
+    return {"value": round(frame_s * 1e3, 1), "unit": "ms/frame", "cores": 1, "kind": "oracle",
+            "sample": f"one 1200x680 frame of the 1M-Gaussian room: projection + binning of all Gaussians "
+                      f"({t1 - t0:.1f} s) and forward+backward compositing of every 3rd tile row "
+                      f"({frac:.3f} of the tiles, {t2 - t1:.1f} s) scaled to the full frame"}
+
+
+if __name__ == "__main__":
+    main()

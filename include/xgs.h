@@ -1,0 +1,243 @@
+/*
+ * xgs.h -- C ABI of the MI355X (gfx950) hot path of the X-GS Perceiver
+ * (arXiv 2603.09632): differentiable tile-based 3D Gaussian splatting of RGB,
+ * depth and semantic channels, grid-sampled distillation targets, and
+ * EMA-updated vector-quantisation codebook assignment.
+ *
+ * Conventions shared by every call
+ *   - All array arguments are DEVICE pointers unless stated otherwise.  The
+ *     caller owns every buffer; the library never allocates device memory and
+ *     keeps no mutable global state.  Scratch space is passed in as a
+ *     workspace whose size comes from the matching *_workspace() query.
+ *   - Every call is asynchronous and ordered on the hipStream_t passed in
+ *     (NULL = the legacy default stream).  No call synchronises the host, so
+ *     every call may be captured into a HIP graph.
+ *   - Arguments are validated on the host before any launch.  On failure the
+ *     call returns a nonzero xgs_status, launches nothing, and
+ *     xgs_last_error() (thread-local) describes the problem.  A failed kernel
+ *     launch returns XGS_ERR_HIP.  No C++ exception crosses the ABI.
+ *   - Device-side overflow (more (tile, Gaussian) instances than the buffers
+ *     hold) sets *status in device memory to a nonzero value; the kernels then
+ *     stay within the buffers.  The caller reads the status after its own sync.
+ *   - Layouts: per-Gaussian arrays are row-major [n][k] (one row per Gaussian,
+ *     as torch stores an (n, k) tensor); images are planar [C][H_s][W_s]; VQ
+ *     arrays are row-major [N][D] and [K][D].  All float data is IEEE binary32.
+ *   - Calls are re-entrant on distinct buffers and streams.
+ *
+ * Readings of the paper fixed by this interface (the paper leaves them open):
+ *   alpha = min(0.99, o G); pairs with alpha < 1/255 are skipped; a pixel stops
+ *   before blending the Gaussian that would take its transmittance below 1e-4;
+ *   Sigma' gets a 0.3 I dilation; background is 0; tiles are 16 x 16 sampled
+ *   pixels; the depth channel is camera z of the Gaussian mean.
+ */
+#ifndef XGS_H
+#define XGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* xgs_stream_t; /* identical to hipStream_t */
+
+typedef enum {
+    XGS_OK = 0,
+    XGS_ERR_INVALID_ARG = 1, /* a size, pointer or alignment the call cannot accept */
+    XGS_ERR_CAPACITY = 2,    /* a caller-provided buffer or workspace is too small   */
+    XGS_ERR_HIP = 3,         /* the HIP runtime reported an error at launch          */
+    XGS_ERR_UNSUPPORTED = 4  /* valid request outside what this build implements     */
+} xgs_status;
+
+enum { XGS_TILE = 16 };                     /* tile edge in sampled pixels          */
+enum { XGS_MAX_C_SEM = 64 };                /* semantic channels per Gaussian        */
+enum { XGS_SPLAT_STRIDE = 8 };              /* floats per projected splat record     */
+enum { XGS_GRID_BILINEAR = 0, XGS_GRID_NEAREST = 1 };
+enum { XGS_VQ_FP32 = 0, XGS_VQ_BF16_RESCORE4 = 1 };
+enum { XGS_EMA_PAPER = 0, XGS_EMA_LAPLACE = 1 };
+
+/* Pinhole camera and sampled grid (host struct, passed by pointer).
+ * viewmat: world -> camera, row-major 4x4, OpenCV axes (x right, y down,
+ * z forward).  The sampled grid is H_s x W_s = ceil(H/stride) x ceil(W/stride);
+ * grid pixel (m, n) is image pixel (off_y + m*stride, off_x + n*stride) with its
+ * centre at (off_x + n*stride + 0.5, off_y + m*stride + 0.5) -- Eq. (sampled_loc).
+ * Gaussians with camera z <= near_plane are culled.  (stride, off_y, off_x) =
+ * (1, 0, 0) renders the dense image.  0 <= off_y, off_x < stride. */
+typedef struct xgs_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float viewmat[16];
+    float near_plane;
+    int32_t stride, off_y, off_x;
+} xgs_camera;
+
+/* A set of 3D Gaussians Theta_i = {mu, Sigma = R S S^T R^T, o, c} with
+ * semantic features f_i (Sec. 3.1, App. A).  Device pointers, row-major:
+ *   means [n][3], log_scales [n][3] (S = diag(exp(l))), quats [n][4]
+ *   (w, x, y, z; any nonzero length, normalised inside), opacity [n]
+ *   (activated, in (0,1]), colors [n][3], features [n][c_sem].
+ * features may be NULL when c_sem == 0.  The same struct with writable
+ * pointers carries gradients (xgs_gaussians_grad). */
+typedef struct xgs_gaussians {
+    int64_t n;
+    int32_t c_sem;
+    int32_t reserved;
+    const float* means;
+    const float* log_scales;
+    const float* quats;
+    const float* opacity;
+    const float* colors;
+    const float* features;
+} xgs_gaussians;
+
+typedef struct xgs_gaussians_grad {
+    int64_t n;
+    int32_t c_sem;
+    int32_t reserved;
+    float* means;       /* [n][3] */
+    float* log_scales;  /* [n][3] */
+    float* quats;       /* [n][4] */
+    float* opacity;     /* [n]    */
+    float* colors;      /* [n][3] */
+    float* features;    /* [n][c_sem] */
+} xgs_gaussians_grad;
+
+/* Output of xgs_project (device buffers of n rows, caller-allocated):
+ *   splat [n][8], 16-byte aligned: mean2d.x, mean2d.y, conic A, B, C (the
+ *     quadratic form A dx^2 + 2B dx dy + C dy^2 of Sigma'^-1), opacity,
+ *     depth (camera z), 0.
+ *   radius [n]: ceil of the larger half-width of the splat's box, 0 = culled.
+ *   tile_rect [n][4] u16: tiles [x0, x1) x [y0, y1) stored x0, y0, x1, y1.
+ *   tiles_touched [n]: (x1-x0)(y1-y0), 0 when culled. */
+typedef struct xgs_projected {
+    float* splat;
+    int32_t* radius;
+    uint16_t* tile_rect;
+    uint32_t* tiles_touched;
+} xgs_projected;
+
+/* Depth-sorted per-tile instance lists produced by xgs_tile_sort:
+ *   keys [max_instances] = (tile_id << 32) | bits(depth) with
+ *     tile_id = ty * tiles_x + tx, sorted ascending, ties by Gaussian index;
+ *   vals [max_instances] = Gaussian index of each key;
+ *   ranges [num_tiles][2] = [first, last+1) of each tile, (0, 0) if empty;
+ *   num_instances: device int64 = number of valid keys M;
+ *   status: device int32, 0 = ok, 1 = the instances exceeded max_instances;
+ *     then num_instances = 0 and every range is empty (nothing is rendered),
+ *     and the caller retries with larger buffers. */
+typedef struct xgs_binning {
+    uint64_t* keys;
+    uint32_t* vals;
+    uint32_t* ranges;
+    int64_t* num_instances;
+    int32_t* status;
+    int64_t max_instances;
+} xgs_binning;
+
+/* ------------------------------------------------------------------ info */
+const char* xgs_status_string(xgs_status s);
+/* Description of the last failure on the calling thread ("" if none). */
+const char* xgs_last_error(void);
+int32_t xgs_version(void);
+/* Sampled-grid geometry of a camera: writes H_s, W_s, tiles_y, tiles_x. */
+xgs_status xgs_grid_dims(const xgs_camera* cam, int32_t* hs, int32_t* ws,
+                         int32_t* tiles_y, int32_t* tiles_x);
+
+/* ---------------------------------------------------------- a1: project
+ * EWA projection (App. A): Sigma = R S S^T R^T, p = W mu + t,
+ * Sigma' = J W Sigma W^T J^T + 0.3 I with J the perspective Jacobian at p
+ * (x/z, y/z clamped to +-1.3 (W/2)/fx, (H/2)/fy), mean2d = (fx x/z + cx,
+ * fy y/z + cy), conic = Sigma'^-1.  The splat's box has half-widths
+ * sqrt(2 ln(255 o) Sigma'_xx), sqrt(2 ln(255 o) Sigma'_yy): outside it
+ * o G < 1/255.  Culled (radius 0, no tiles): z <= near, o < 1/255, or a box
+ * that misses the sampled grid.  One thread per Gaussian; n may be 0. */
+xgs_status xgs_project(const xgs_gaussians* g, const xgs_camera* cam, xgs_projected* out,
+                       xgs_stream_t stream);
+
+/* ------------------------------------------------------- a2: tile sort
+ * Binning and depth sort ("depth-sorted Gaussians", Sec. 3.1): exclusive scan
+ * of tiles_touched, emission of one key per (tile, Gaussian) in Gaussian
+ * order, stable LSD radix sort over the 32 + ceil(log2(tiles)) key bits, and
+ * per-tile ranges.  Reads p->tile_rect, p->tiles_touched and the depth of
+ * p->splat.  ws must hold xgs_tile_sort_workspace(n, max_instances, tiles)
+ * bytes, 256-byte aligned. */
+size_t xgs_tile_sort_workspace(int64_t n, int64_t max_instances, int32_t num_tiles);
+xgs_status xgs_tile_sort(const xgs_projected* p, const xgs_camera* cam, int64_t n, void* ws,
+                         size_t ws_bytes, xgs_binning* b, xgs_stream_t stream);
+
+/* -------------------------------------------------- a3: render forward
+ * Front-to-back alpha blending, Eq. (rendering): for every grid pixel walk its
+ * tile's list, alpha = min(0.99, o exp(-q/2)); skip alpha < 1/255; stop
+ * before blending when T (1 - alpha) < 1e-4; out += alpha T [rgb, depth, f].
+ * out [4 + c_sem][H_s][W_s] (channel order R, G, B, depth, semantic...),
+ * final_T [H_s][W_s] (transmittance after the last blended Gaussian),
+ * n_last [H_s][W_s] (list position after the last blended Gaussian). */
+xgs_status xgs_render_fwd(const xgs_gaussians* g, const xgs_projected* p, const xgs_binning* b,
+                          const xgs_camera* cam, float* out, float* final_T, int32_t* n_last,
+                          xgs_stream_t stream);
+
+/* ------------------------------------------------- a4: render backward
+ * Gradient of L = sum d_out * out with respect to every parameter group.  Per
+ * pixel the walk runs back to front from n_last, recovering the transmittance
+ * before each Gaussian as T / (1 - alpha) from final_T (nothing per pair is
+ * stored); dL/dalpha_k = T_k (g . c_k) - S_k / (1 - alpha_k).  Per-Gaussian
+ * sums are reduced across each wavefront before one atomic add per value; a
+ * second kernel carries (mean2d, conic, depth) gradients back through the
+ * projection.  grads: all six arrays are overwritten (the call zeroes them).
+ * flags: XGS_BWD_FEATURES_ONLY computes only d_features (geometry frozen,
+ * Sec. 3.2.2 "decouple"); the other gradient pointers may then be NULL.
+ * ws must hold xgs_render_bwd_workspace(n) bytes, 256-byte aligned. */
+enum { XGS_BWD_ALL = 0, XGS_BWD_FEATURES_ONLY = 1 };
+size_t xgs_render_bwd_workspace(int64_t n);
+xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected* p, const xgs_binning* b,
+                          const xgs_camera* cam, const float* d_out, const float* final_T,
+                          const int32_t* n_last, int32_t flags, xgs_gaussians_grad* grads,
+                          void* ws, size_t ws_bytes, xgs_stream_t stream);
+
+/* -------------------------------------------------- a5: grid-sampled targets
+ * App. D, Eq. (target_continuous): for grid pixel (m, n) at image pixel
+ * (u, v) = (off_y + m s, off_x + n s), u~ = u (Hf-1)/max(H-1,1),
+ * v~ = v (Wf-1)/max(W-1,1).  NEAREST takes P at (round u~, round v~) (round
+ * half to even, exact integer arithmetic); BILINEAR interpolates P at
+ * (u~, v~).  V = 1 inside the image; V = 0 and G = 0 where u >= H or v >= W.
+ * P [D][Hf][Wf], G [D][H_s][W_s], V [H_s][W_s] (V may be NULL). */
+xgs_status xgs_grid_sample(const float* P, int32_t D, int32_t Hf, int32_t Wf, int32_t H,
+                           int32_t W, int32_t stride, int32_t off_y, int32_t off_x, int32_t mode,
+                           float* G, uint8_t* V, xgs_stream_t stream);
+
+/* ------------------------------------------------------ a6: VQ assignment
+ * a_n = argmin_l ||x_n - E_l||^2 (Sec. 3.2.2), ties to the lowest l.
+ * XGS_VQ_FP32: direct FP32 sum of (x - e)^2 over every codeword.
+ * XGS_VQ_BF16_RESCORE4: ||e^||^2 - 2 x^.e^ with bf16 x^, e^ on MFMA (FP32
+ * accumulation) keeps each row's 4 best codewords, which are then rescored
+ * with the direct FP32 form.  E_bf16 [K][D] and e_norm2 [K] must hold
+ * xgs_vq_prepare's output for E (xgs_vq_ema_update refreshes them).
+ * BF16 requires D % 16 == 0.  idx [N] int32, dist [N] = FP32 squared
+ * distance of the chosen codeword.  ws: xgs_vq_assign_workspace bytes. */
+size_t xgs_vq_assign_workspace(int64_t N, int32_t D, int32_t K, int32_t precision);
+xgs_status xgs_vq_prepare(const float* E, int32_t K, int32_t D, uint16_t* E_bf16, float* e_norm2,
+                          xgs_stream_t stream);
+xgs_status xgs_vq_assign(const float* X, int64_t N, int32_t D, const float* E,
+                         const uint16_t* E_bf16, const float* e_norm2, int32_t K,
+                         int32_t precision, int32_t* idx, float* dist, void* ws, size_t ws_bytes,
+                         xgs_stream_t stream);
+
+/* --------------------------------------------------------- a7: EMA update
+ * Eq. (ema_update): c_l = #{a_n = l}, s_l = sum_{a_n = l} x_n,
+ * N <- decay N + (1-decay) c, M <- decay M + (1-decay) s, then
+ * PAPER: E_l = M_l / (N_l + eps); LAPLACE: E_l = M_l / Ntilde_l with
+ * Ntilde_l = (N_l + eps) / (n + K eps) * n, n = sum_l N_l.  Sums are formed
+ * in a fixed order (rows sorted stably by code), so the result is bitwise
+ * reproducible.  Refreshes E_bf16 and e_norm2.  counts [K] (may be NULL)
+ * receives c.  ws: xgs_vq_ema_workspace bytes. */
+size_t xgs_vq_ema_workspace(int64_t N, int32_t D, int32_t K);
+xgs_status xgs_vq_ema_update(const float* X, const int32_t* idx, int64_t N, int32_t D, int32_t K,
+                             float* N_ema, float* M_ema, float* E, uint16_t* E_bf16,
+                             float* e_norm2, float* counts, float decay, float eps, int32_t mode,
+                             void* ws, size_t ws_bytes, xgs_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XGS_H */

@@ -144,7 +144,7 @@ class Render:
     out: np.ndarray       # [C, Hs, Ws]
     final_T: np.ndarray   # [Hs, Ws]
     n_last: np.ndarray    # [Hs, Ws]
-    amb: np.ndarray       # [3, Hs, Ws] skip, stop, depth-gap ambiguity measures
+    amb: np.ndarray       # [4, Hs, Ws] skip, stop, depth-gap measures; blend signature
     chan: np.ndarray
 
 
@@ -155,7 +155,8 @@ def composite_fwd(proj: Projection, opacity, chan, order, ranges, cam, tile_mask
     out = np.zeros((C, hs, ws))
     fT = np.ones((hs, ws))
     nl = np.zeros((hs, ws), np.int64)
-    amb = np.full((3, hs, ws), np.inf)
+    amb = np.full((4, hs, ws), np.inf)
+    amb[3] = 0.0
     tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, dtype=np.uint8)
     lib().orc_composite_fwd(ctypes.c_int64(len(opacity)), _p(_f64(proj.mean2d)),
                             _p(_f64(proj.conic)), _p(_f64(opacity)), _p(_f64(chan)),

@@ -256,7 +256,9 @@ int64_t orc_bin(int64_t n, const int32_t* rect, const uint32_t* depth_bits, int3
  * the list position after the last Gaussian blended.  The three ambiguity
  * measures are minima over the walk of |255 o G - 1| (skip decision),
  * |T'/1e-4 - 1| (stop decision) and the relative depth gap between consecutive
- * blended Gaussians.
+ * blended Gaussians.  amb[3] is a signature of the blended sequence,
+ * sum over blended Gaussians of (index + 1) * (ordinal + 1), exact in double;
+ * it changes whenever a skip, stop or ordering decision changes.
  */
 static double walk_pixel(double px, double py, const uint32_t* list, int64_t len,
                          const double* mean2d, const double* conic, const double* opac,
@@ -265,7 +267,8 @@ static double walk_pixel(double px, double py, const uint32_t* list, int64_t len
     double T = 1.0;
     for (int c = 0; c < C; ++c) out[c] = 0.0;
     *n_last = 0;
-    double a_skip = INFINITY, a_stop = INFINITY, a_depth = INFINITY, prev_z = NAN;
+    double a_skip = INFINITY, a_stop = INFINITY, a_depth = INFINITY, prev_z = NAN, sig = 0.0;
+    double ordinal = 0.0;
     for (int64_t j = 0; j < len; ++j) {
         uint32_t i = list[j];
         double dx = px - mean2d[2 * i], dy = py - mean2d[2 * i + 1];
@@ -292,15 +295,17 @@ static double walk_pixel(double px, double py, const uint32_t* list, int64_t len
         }
         T = Tn;
         *n_last = j + 1;
+        ordinal += 1.0;
+        sig += ((double)i + 1.0) * ordinal;
     }
-    if (amb) { amb[0] = a_skip; amb[1] = a_stop; amb[2] = a_depth; }
+    if (amb) { amb[0] = a_skip; amb[1] = a_stop; amb[2] = a_depth; amb[3] = sig; }
     return T;
 }
 
 /*
  * Tiled forward composite over the sampled grid.  order/ranges come from
  * orc_bin.  Outputs out[C][Hs][Ws], final_T[Hs][Ws], n_last[Hs][Ws] (position
- * within the tile list), amb[3][Hs][Ws].  tile_mask (optional, [T]) restricts
+ * within the tile list), amb[4][Hs][Ws] (see walk_pixel).  tile_mask (optional, [T]) restricts
  * the work to tiles with a nonzero entry; other pixels are left untouched.
  */
 int orc_composite_fwd(int64_t n, const double* mean2d, const double* conic, const double* opac,
@@ -317,13 +322,13 @@ int orc_composite_fwd(int64_t n, const double* mean2d, const double* conic, cons
             if (tile_mask && !tile_mask[t]) continue;
             double px = k.ox + (double)nn * k.s + 0.5, py = k.oy + (double)m * k.s + 0.5;
             uint32_t b = ranges[2 * t], e = ranges[2 * t + 1];
-            double a3[3]; int64_t nl;
+            double a3[4]; int64_t nl;
             double T = walk_pixel(px, py, order + b, (int64_t)e - b, mean2d, conic, opac, chan,
                                   depth, C, acc, &nl, a3);
             int64_t pix = (int64_t)m * k.Ws + nn;
             for (int c = 0; c < C; ++c) out[c * HW + pix] = acc[c];
             final_T[pix] = T; n_last[pix] = nl;
-            if (amb) for (int j = 0; j < 3; ++j) amb[j * HW + pix] = a3[j];
+            if (amb) for (int j = 0; j < 4; ++j) amb[j * HW + pix] = a3[j];
         }
     free(acc);
     return 0;

@@ -1,0 +1,270 @@
+"""Python binding of libxgs (include/xgs.h): the MI355X hot path of the X-GS
+Perceiver (arXiv 2603.09632).
+
+Every function here only marshals torch tensors (device memory, streams) into
+the C ABI of the same name; all arithmetic runs in the HIP kernels.  There is
+no CPU fallback: without the built library the import fails.
+
+Conventions: tensors live on the current CUDA (HIP) device, are contiguous
+float32 unless stated, and calls are enqueued on torch's current stream.
+Unsigned device arrays of the ABI are held in signed torch tensors of the same
+width (uint16 -> int16, uint32 -> int32, uint64 -> int64).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import XgsBinning, XgsCamera, XgsError, XgsGaussians, XgsProjected, check
+
+lib = _lib.load()
+
+TILE = 16
+SPLAT_STRIDE = 8
+GRID_BILINEAR, GRID_NEAREST = 0, 1
+VQ_FP32, VQ_BF16_RESCORE4 = 0, 1
+EMA_PAPER, EMA_LAPLACE = 0, 1
+BWD_ALL, BWD_FEATURES_ONLY = 0, 1
+
+__all__ = [
+    "XgsError", "Gaussians", "Projected", "Binning", "camera", "camera_from", "grid_dims",
+    "xgs_project", "alloc_binning", "xgs_tile_sort", "xgs_render_fwd", "xgs_render_bwd",
+    "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_ema_update", "render",
+]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise XgsError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise XgsError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------- camera
+def camera(width, height, fx, fy, cx, cy, viewmat=None, near=0.2, stride=1, off_y=0, off_x=0) -> XgsCamera:
+    c = XgsCamera()
+    c.width, c.height = int(width), int(height)
+    c.fx, c.fy, c.cx, c.cy = float(fx), float(fy), float(cx), float(cy)
+    vm = [1.0, 0, 0, 0, 0, 1.0, 0, 0, 0, 0, 1.0, 0, 0, 0, 0, 1.0] if viewmat is None else \
+        [float(v) for v in torch.as_tensor(viewmat, dtype=torch.float64).reshape(16).tolist()]
+    for i, v in enumerate(vm):
+        c.viewmat[i] = v
+    c.near_plane = float(near)
+    c.stride, c.off_y, c.off_x = int(stride), int(off_y), int(off_x)
+    return c
+
+
+def camera_from(obj) -> XgsCamera:
+    """From any object with width/height/fx/fy/cx/cy/viewmat/near/stride/off_y/off_x."""
+    if isinstance(obj, XgsCamera):
+        return obj
+    return camera(obj.width, obj.height, obj.fx, obj.fy, obj.cx, obj.cy, obj.viewmat,
+                  getattr(obj, "near", 0.2), getattr(obj, "stride", 1), getattr(obj, "off_y", 0),
+                  getattr(obj, "off_x", 0))
+
+
+def grid_dims(cam) -> tuple[int, int, int, int]:
+    """(H_s, W_s, tiles_y, tiles_x) of the sampled grid."""
+    c = camera_from(cam)
+    hs, ws, ty, tx = (ctypes.c_int32() for _ in range(4))
+    check(lib.xgs_grid_dims(ctypes.byref(c), ctypes.byref(hs), ctypes.byref(ws), ctypes.byref(ty),
+                            ctypes.byref(tx)), "xgs_grid_dims")
+    return hs.value, ws.value, ty.value, tx.value
+
+
+# ------------------------------------------------------------- Gaussians
+@dataclass
+class Gaussians:
+    means: torch.Tensor       # [n,3]
+    log_scales: torch.Tensor  # [n,3]
+    quats: torch.Tensor       # [n,4] (w,x,y,z)
+    opacity: torch.Tensor     # [n]   activated
+    colors: torch.Tensor      # [n,3]
+    features: torch.Tensor    # [n,c_sem]
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def c_sem(self) -> int:
+        return int(self.features.shape[1]) if self.features is not None and self.features.dim() == 2 else 0
+
+    def struct(self) -> XgsGaussians:
+        s = XgsGaussians()
+        s.n, s.c_sem = self.n, self.c_sem
+        s.means, s.log_scales, s.quats, s.opacity, s.colors = (
+            _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats), _ptr(self.opacity),
+            _ptr(self.colors))
+        s.features = _ptr(self.features) if self.c_sem > 0 else None
+        return s
+
+    @staticmethod
+    def empty_like(g: "Gaussians") -> "Gaussians":
+        return Gaussians(*(torch.empty_like(t) for t in (g.means, g.log_scales, g.quats, g.opacity,
+                                                          g.colors, g.features)))
+
+
+@dataclass
+class Projected:
+    splat: torch.Tensor          # [n,8] f32
+    radius: torch.Tensor         # [n]   i32
+    tile_rect: torch.Tensor      # [n,4] u16 (as int16)
+    tiles_touched: torch.Tensor  # [n]   u32 (as int32)
+
+    @staticmethod
+    def alloc(n: int, device=None) -> "Projected":
+        d = device or torch.device("cuda")
+        return Projected(torch.empty((n, SPLAT_STRIDE), dtype=torch.float32, device=d),
+                         torch.empty(n, dtype=torch.int32, device=d),
+                         torch.empty((n, 4), dtype=torch.int16, device=d),
+                         torch.empty(n, dtype=torch.int32, device=d))
+
+    def struct(self) -> XgsProjected:
+        s = XgsProjected()
+        s.splat, s.radius, s.tile_rect, s.tiles_touched = (_ptr(self.splat), _ptr(self.radius),
+                                                           _ptr(self.tile_rect), _ptr(self.tiles_touched))
+        return s
+
+
+@dataclass
+class Binning:
+    keys: torch.Tensor           # [cap] u64 (as int64)
+    vals: torch.Tensor           # [cap] u32 (as int32)
+    ranges: torch.Tensor         # [tiles,2] u32 (as int32)
+    num_instances: torch.Tensor  # [1] int64
+    status: torch.Tensor         # [1] int32
+    workspace: torch.Tensor      # u8
+    max_instances: int
+
+    def struct(self) -> XgsBinning:
+        s = XgsBinning()
+        s.keys, s.vals, s.ranges, s.num_instances, s.status = (
+            _ptr(self.keys), _ptr(self.vals), _ptr(self.ranges), _ptr(self.num_instances), _ptr(self.status))
+        s.max_instances = int(self.max_instances)
+        return s
+
+
+def xgs_project(g: Gaussians, cam, out: Optional[Projected] = None, stream=None) -> Projected:
+    c = camera_from(cam)
+    out = out or Projected.alloc(g.n, g.means.device)
+    gs, ps = g.struct(), out.struct()
+    check(lib.xgs_project(ctypes.byref(gs), ctypes.byref(c), ctypes.byref(ps), _stream(stream)), "xgs_project")
+    return out
+
+
+def alloc_binning(n: int, max_instances: int, cam, device=None) -> Binning:
+    d = device or torch.device("cuda")
+    _, _, ty, tx = grid_dims(cam)
+    cap = max(int(max_instances), 1)
+    ws = int(lib.xgs_tile_sort_workspace(n, cap, ty * tx))
+    return Binning(torch.empty(cap, dtype=torch.int64, device=d), torch.empty(cap, dtype=torch.int32, device=d),
+                   torch.empty((ty * tx, 2), dtype=torch.int32, device=d),
+                   torch.zeros(1, dtype=torch.int64, device=d), torch.zeros(1, dtype=torch.int32, device=d),
+                   torch.empty(max(ws, 1), dtype=torch.uint8, device=d), cap)
+
+
+def xgs_tile_sort(p: Projected, cam, n: int, b: Binning, stream=None) -> Binning:
+    c = camera_from(cam)
+    ps, bs = p.struct(), b.struct()
+    check(lib.xgs_tile_sort(ctypes.byref(ps), ctypes.byref(c), int(n), _ptr(b.workspace), b.workspace.numel(),
+                            ctypes.byref(bs), _stream(stream)), "xgs_tile_sort")
+    return b
+
+
+def xgs_render_fwd(g: Gaussians, p: Projected, b: Binning, cam, out=None, final_T=None, n_last=None,
+                   stream=None):
+    c = camera_from(cam)
+    hs, ws, _, _ = grid_dims(c)
+    dev = g.means.device
+    out = out if out is not None else torch.empty((4 + g.c_sem, hs, ws), dtype=torch.float32, device=dev)
+    final_T = final_T if final_T is not None else torch.empty((hs, ws), dtype=torch.float32, device=dev)
+    n_last = n_last if n_last is not None else torch.empty((hs, ws), dtype=torch.int32, device=dev)
+    gs, ps, bs = g.struct(), p.struct(), b.struct()
+    check(lib.xgs_render_fwd(ctypes.byref(gs), ctypes.byref(ps), ctypes.byref(bs), ctypes.byref(c), _ptr(out),
+                             _ptr(final_T), _ptr(n_last), _stream(stream)), "xgs_render_fwd")
+    return out, final_T, n_last
+
+
+def xgs_render_bwd(g: Gaussians, p: Projected, b: Binning, cam, d_out, final_T, n_last,
+                   flags: int = BWD_ALL, grads: Optional[Gaussians] = None, workspace=None,
+                   stream=None) -> Gaussians:
+    c = camera_from(cam)
+    grads = grads or Gaussians.empty_like(g)
+    need = int(lib.xgs_render_bwd_workspace(g.n))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=g.means.device)
+    gs, ps, bs, gr = g.struct(), p.struct(), b.struct(), grads.struct()
+    check(lib.xgs_render_bwd(ctypes.byref(gs), ctypes.byref(ps), ctypes.byref(bs), ctypes.byref(c), _ptr(d_out),
+                             _ptr(final_T), _ptr(n_last), int(flags), ctypes.byref(gr), _ptr(workspace),
+                             workspace.numel(), _stream(stream)), "xgs_render_bwd")
+    return grads
+
+
+def xgs_grid_sample(P: torch.Tensor, H: int, W: int, stride: int = 1, off_y: int = 0, off_x: int = 0,
+                    mode: int = GRID_BILINEAR, G=None, V=None, stream=None):
+    D, Hf, Wf = P.shape
+    hs, ws = -(-H // stride), -(-W // stride)
+    G = G if G is not None else torch.empty((D, hs, ws), dtype=torch.float32, device=P.device)
+    V = V if V is not None else torch.empty((hs, ws), dtype=torch.uint8, device=P.device)
+    check(lib.xgs_grid_sample(_ptr(P), D, Hf, Wf, int(H), int(W), int(stride), int(off_y), int(off_x), int(mode),
+                              _ptr(G), _ptr(V), _stream(stream)), "xgs_grid_sample")
+    return G, V
+
+
+def xgs_vq_prepare(E: torch.Tensor, E_bf16=None, e_norm2=None, stream=None):
+    K, D = E.shape
+    E_bf16 = E_bf16 if E_bf16 is not None else torch.empty((K, D), dtype=torch.int16, device=E.device)
+    e_norm2 = e_norm2 if e_norm2 is not None else torch.empty(K, dtype=torch.float32, device=E.device)
+    check(lib.xgs_vq_prepare(_ptr(E), K, D, _ptr(E_bf16), _ptr(e_norm2), _stream(stream)), "xgs_vq_prepare")
+    return E_bf16, e_norm2
+
+
+def xgs_vq_assign(X: torch.Tensor, E: torch.Tensor, E_bf16=None, e_norm2=None, precision: int = VQ_BF16_RESCORE4,
+                  idx=None, dist=None, stream=None):
+    N, D = X.shape
+    K = E.shape[0]
+    idx = idx if idx is not None else torch.empty(N, dtype=torch.int32, device=X.device)
+    dist = dist if dist is not None else torch.empty(N, dtype=torch.float32, device=X.device)
+    check(lib.xgs_vq_assign(_ptr(X), N, D, _ptr(E), _ptr(E_bf16), _ptr(e_norm2), K, int(precision), _ptr(idx),
+                            _ptr(dist), None, 0, _stream(stream)), "xgs_vq_assign")
+    return idx, dist
+
+
+def xgs_vq_ema_update(X, idx, N_ema, M_ema, E, E_bf16=None, e_norm2=None, decay: float = 0.99,
+                      eps: float = 1e-5, mode: int = EMA_LAPLACE, counts=None, workspace=None, stream=None):
+    N, D = X.shape
+    K = E.shape[0]
+    need = int(lib.xgs_vq_ema_workspace(N, D, K))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
+    counts = counts if counts is not None else torch.empty(K, dtype=torch.float32, device=X.device)
+    check(lib.xgs_vq_ema_update(_ptr(X), _ptr(idx), N, D, K, _ptr(N_ema), _ptr(M_ema), _ptr(E), _ptr(E_bf16),
+                                _ptr(e_norm2), _ptr(counts), float(decay), float(eps), int(mode),
+                                _ptr(workspace), workspace.numel(), _stream(stream)), "xgs_vq_ema_update")
+    return counts
+
+
+def render(g: Gaussians, cam, max_instances: Optional[int] = None, stream=None):
+    """project -> tile_sort -> render_fwd.  Without max_instances the exact
+    instance count is read back once (a host synchronisation)."""
+    c = camera_from(cam)
+    p = xgs_project(g, c, stream=stream)
+    if max_instances is None:
+        max_instances = int(p.tiles_touched.to(torch.int64).sum().item())
+    b = alloc_binning(g.n, max_instances, c, g.means.device)
+    xgs_tile_sort(p, c, g.n, b, stream=stream)
+    out, final_T, n_last = xgs_render_fwd(g, p, b, c, stream=stream)
+    return out, final_T, n_last, p, b

@@ -1,0 +1,123 @@
+// a5: grid-sampled distillation targets from a low-resolution feature map
+// (App. D, Eq. (sampled_loc) and Eq. (target_continuous)).  The kernel is
+// write-bound: P (a few MB) stays in cache while G (D x H_s x W_s floats) is
+// streamed out with 16-byte non-temporal stores.  Each thread owns four
+// consecutive grid pixels, computes their source coordinates once, and loops
+// over a chunk of channels.
+#include "common.h"
+
+namespace xgs {
+
+struct Src {
+    int y0, y1, x0, x1;
+    float wy, wx;
+    bool valid;
+};
+
+__device__ __forceinline__ Src source_of(int64_t p, int Ws, int H, int W, int Hf, int Wf, int s,
+                                         int oy, int ox, int mode) {
+    Src r;
+    const int m = (int)(p / Ws), n = (int)(p - (int64_t)m * Ws);
+    const int64_t u = (int64_t)oy + (int64_t)m * s, v = (int64_t)ox + (int64_t)n * s;
+    r.valid = u < H && v < W;
+    const int64_t by = H > 1 ? H - 1 : 1, bx = W > 1 ? W - 1 : 1;
+    const int64_t ay = u * (Hf - 1), ax = v * (Wf - 1);
+    const int64_t qy = ay / by, ry = ay - qy * by;
+    const int64_t qx = ax / bx, rx = ax - qx * bx;
+    if (mode == XGS_GRID_NEAREST) {
+        // round half to even of ay/by and ax/bx, exactly
+        int64_t iy = qy + ((2 * ry > by) || (2 * ry == by && (qy & 1)));
+        int64_t ix = qx + ((2 * rx > bx) || (2 * rx == bx && (qx & 1)));
+        r.y0 = r.y1 = (int)(iy < Hf - 1 ? iy : Hf - 1);
+        r.x0 = r.x1 = (int)(ix < Wf - 1 ? ix : Wf - 1);
+        r.wy = r.wx = 0.f;
+    } else {
+        r.y0 = (int)(qy < Hf - 1 ? qy : Hf - 1);
+        r.x0 = (int)(qx < Wf - 1 ? qx : Wf - 1);
+        r.y1 = r.y0 + 1 < Hf ? r.y0 + 1 : Hf - 1;
+        r.x1 = r.x0 + 1 < Wf ? r.x0 + 1 : Wf - 1;
+        r.wy = (float)ry / (float)by;
+        r.wx = (float)rx / (float)bx;
+    }
+    if (!r.valid) { r.y0 = r.y1 = r.x0 = r.x1 = 0; }
+    return r;
+}
+
+__device__ __forceinline__ float sample(const float* __restrict__ Pd, int Wf, const Src& s) {
+    if (!s.valid) return 0.f;
+    const float p00 = Pd[s.y0 * Wf + s.x0], p01 = Pd[s.y0 * Wf + s.x1];
+    const float p10 = Pd[s.y1 * Wf + s.x0], p11 = Pd[s.y1 * Wf + s.x1];
+    const float top = p00 + s.wx * (p01 - p00);
+    const float bot = p10 + s.wx * (p11 - p10);
+    return top + s.wy * (bot - top);
+}
+
+constexpr int kChanChunk = 8;
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <bool VEC>
+__global__ void __launch_bounds__(256) grid_sample_kernel(const float* __restrict__ P, int D, int Hf,
+                                                         int Wf, int H, int W, int s, int oy, int ox,
+                                                         int mode, int Hs, int Ws,
+                                                         float* __restrict__ G, uint8_t* __restrict__ V) {
+    const int64_t hw = (int64_t)Hs * Ws;
+    const int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (p0 >= hw) return;
+    Src src[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t p = p0 + k < hw ? p0 + k : hw - 1;
+        src[k] = source_of(p, Ws, H, W, Hf, Wf, s, oy, ox, mode);
+    }
+    const int d0 = blockIdx.y * kChanChunk;
+    const int d1 = d0 + kChanChunk < D ? d0 + kChanChunk : D;
+    const int64_t plane = (int64_t)Hf * Wf;
+    for (int d = d0; d < d1; ++d) {
+        const float* Pd = P + d * plane;
+        f32x4_t v = {sample(Pd, Wf, src[0]), sample(Pd, Wf, src[1]), sample(Pd, Wf, src[2]),
+                     sample(Pd, Wf, src[3])};
+        float* out = G + (int64_t)d * hw + p0;
+        if (VEC) {
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4_t*>(out));
+        } else {
+            for (int k = 0; k < 4 && p0 + k < hw; ++k) __builtin_nontemporal_store(v[k], out + k);
+        }
+    }
+    if (V && blockIdx.y == 0) {
+        for (int k = 0; k < 4 && p0 + k < hw; ++k) V[p0 + k] = src[k].valid ? 1 : 0;
+    }
+}
+
+}  // namespace xgs
+
+using namespace xgs;
+
+extern "C" xgs_status xgs_grid_sample(const float* P, int32_t D, int32_t Hf, int32_t Wf, int32_t H,
+                                      int32_t W, int32_t stride, int32_t off_y, int32_t off_x,
+                                      int32_t mode, float* G, uint8_t* V, xgs_stream_t stream) {
+    clear_error();
+    if (D < 0 || Hf < 1 || Wf < 1 || H < 1 || W < 1 || stride < 1)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_grid_sample: sizes must be positive (D >= 0)");
+    if (off_y < 0 || off_x < 0 || off_y >= stride || off_x >= stride)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_grid_sample: offsets must lie in [0, stride)");
+    if (mode != XGS_GRID_BILINEAR && mode != XGS_GRID_NEAREST)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_grid_sample: unknown mode");
+    if ((int64_t)Hf * Wf * D >= (int64_t(1) << 31))
+        return fail(XGS_ERR_UNSUPPORTED, "xgs_grid_sample: feature map above 2^31 elements");
+    const int Hs = (H + stride - 1) / stride, Ws = (W + stride - 1) / stride;
+    const int64_t hw = (int64_t)Hs * Ws;
+    if (D > 0 && (!P || !G)) return fail(XGS_ERR_INVALID_ARG, "xgs_grid_sample: null P or G");
+    if (D == 0 && !V) return XGS_OK;
+    const bool vec = (hw % 4 == 0) && aligned(G, 16);
+    const unsigned bx = (unsigned)((hw + 1023) / 1024);
+    const unsigned by = (unsigned)(D > 0 ? (D + kChanChunk - 1) / kChanChunk : 1);
+    if (by > 65535) return fail(XGS_ERR_UNSUPPORTED, "xgs_grid_sample: too many channels");
+    hipStream_t st = (hipStream_t)stream;
+    if (vec)
+        hipLaunchKernelGGL(grid_sample_kernel<true>, dim3(bx, by), dim3(256), 0, st, P, D, Hf, Wf, H, W,
+                           stride, off_y, off_x, mode, Hs, Ws, G, V);
+    else
+        hipLaunchKernelGGL(grid_sample_kernel<false>, dim3(bx, by), dim3(256), 0, st, P, D, Hf, Wf, H, W,
+                           stride, off_y, off_x, mode, Hs, Ws, G, V);
+    return check_launch("xgs_grid_sample");
+}

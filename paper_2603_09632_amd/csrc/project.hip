@@ -1,0 +1,146 @@
+// a1: EWA projection of 3D Gaussians to screen-space splats (App. A), plus
+// the opacity-aware tile rectangle.  One thread per Gaussian; every input row
+// is read once with full cache lines (row-major [n][k] rows are contiguous
+// across a wavefront) and each output record is written once.
+#include "common.h"
+
+namespace xgs {
+
+struct CamDev {
+    float fx, fy, cx, cy, near_, limx, limy;
+    float R[9], t[3];
+    int s, oy, ox, hs, ws;
+};
+
+__global__ void __launch_bounds__(256) project_kernel(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const float* __restrict__ opacity, CamDev c,
+    float4* __restrict__ splat, int32_t* __restrict__ radius, uint2* __restrict__ tile_rect,
+    uint32_t* __restrict__ touched) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+    const float o = opacity[i];
+    float px = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
+    float py = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
+    float pz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
+
+    float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = make_float4(0.f, o, pz, 0.f);
+    uint2 rect = make_uint2(0u, 0u);
+    int32_t rad = 0;
+    uint32_t tt = 0;
+    bool ok = pz > c.near_ && o >= kAlphaMin;
+    if (ok) {
+        // Sigma = M M^T with M = R(q) diag(exp l)
+        float4 q = quats[i];
+        float inv = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+        float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
+        float R00 = 1.f - 2.f * (y * y + z * z), R01 = 2.f * (x * y - w * z), R02 = 2.f * (x * z + w * y);
+        float R10 = 2.f * (x * y + w * z), R11 = 1.f - 2.f * (x * x + z * z), R12 = 2.f * (y * z - w * x);
+        float R20 = 2.f * (x * z - w * y), R21 = 2.f * (y * z + w * x), R22 = 1.f - 2.f * (x * x + y * y);
+        float sx = __expf(log_scales[3 * i]), sy = __expf(log_scales[3 * i + 1]),
+              sz = __expf(log_scales[3 * i + 2]);
+        // rows of T = Rv M  (camera-frame factor, Sigma_cam = T T^T)
+        float M00 = R00 * sx, M01 = R01 * sy, M02 = R02 * sz;
+        float M10 = R10 * sx, M11 = R11 * sy, M12 = R12 * sz;
+        float M20 = R20 * sx, M21 = R21 * sy, M22 = R22 * sz;
+        float T0[3], T1[3], T2[3];
+        T0[0] = c.R[0] * M00 + c.R[1] * M10 + c.R[2] * M20;
+        T0[1] = c.R[0] * M01 + c.R[1] * M11 + c.R[2] * M21;
+        T0[2] = c.R[0] * M02 + c.R[1] * M12 + c.R[2] * M22;
+        T1[0] = c.R[3] * M00 + c.R[4] * M10 + c.R[5] * M20;
+        T1[1] = c.R[3] * M01 + c.R[4] * M11 + c.R[5] * M21;
+        T1[2] = c.R[3] * M02 + c.R[4] * M12 + c.R[5] * M22;
+        T2[0] = c.R[6] * M00 + c.R[7] * M10 + c.R[8] * M20;
+        T2[1] = c.R[6] * M01 + c.R[7] * M11 + c.R[8] * M21;
+        T2[2] = c.R[6] * M02 + c.R[7] * M12 + c.R[8] * M22;
+        // J at the guarded point
+        float iz = 1.f / pz;
+        float u = px * iz, v = py * iz;
+        float tx = fminf(fmaxf(u, -c.limx), c.limx) * pz;
+        float ty = fminf(fmaxf(v, -c.limy), c.limy) * pz;
+        float J00 = c.fx * iz, J02 = -c.fx * tx * iz * iz;
+        float J11 = c.fy * iz, J12 = -c.fy * ty * iz * iz;
+        // U = J T (2x3);  Sigma' = U U^T + 0.3 I
+        float U0[3], U1[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            U0[k] = J00 * T0[k] + J02 * T2[k];
+            U1[k] = J11 * T1[k] + J12 * T2[k];
+        }
+        float a = U0[0] * U0[0] + U0[1] * U0[1] + U0[2] * U0[2] + kDilation;
+        float b = U0[0] * U1[0] + U0[1] * U1[1] + U0[2] * U1[2];
+        float cc = U1[0] * U1[0] + U1[1] * U1[1] + U1[2] * U1[2] + kDilation;
+        float det = a * cc - b * b;
+        ok = det > 0.f;
+        if (ok) {
+            float id = 1.f / det;
+            float mx2 = c.fx * u + c.cx, my2 = c.fy * v + c.cy;
+            float tau = 2.f * __logf(255.f * o);
+            float ex = sqrtf(tau * a), ey = sqrtf(tau * cc);
+            // sampled-pixel index range whose centres lie in [m - e, m + e]
+            float fs = (float)c.s;
+            float nlo = ceilf((mx2 - ex - (float)c.ox - 0.5f) / fs);
+            float nhi = floorf((mx2 + ex - (float)c.ox - 0.5f) / fs);
+            float mlo = ceilf((my2 - ey - (float)c.oy - 0.5f) / fs);
+            float mhi = floorf((my2 + ey - (float)c.oy - 0.5f) / fs);
+            nlo = fmaxf(nlo, 0.f);
+            mlo = fmaxf(mlo, 0.f);
+            nhi = fminf(nhi, (float)(c.ws - 1));
+            mhi = fminf(mhi, (float)(c.hs - 1));
+            ok = (nlo <= nhi) && (mlo <= mhi);
+            if (ok) {
+                int x0 = (int)nlo / kTile, x1 = (int)nhi / kTile + 1;
+                int y0 = (int)mlo / kTile, y1 = (int)mhi / kTile + 1;
+                rect = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
+                tt = (uint32_t)((x1 - x0) * (y1 - y0));
+                rad = (int32_t)ceilf(fmaxf(ex, ey));
+                if (rad < 1) rad = 1;
+                s0 = make_float4(mx2, my2, cc * id, -b * id);
+                s1 = make_float4(a * id, o, pz, 0.f);
+            }
+        }
+    }
+    splat[2 * i] = s0;
+    splat[2 * i + 1] = s1;
+    radius[i] = rad;
+    tile_rect[i] = rect;
+    touched[i] = tt;
+}
+
+}  // namespace xgs
+
+using namespace xgs;
+
+extern "C" xgs_status xgs_project(const xgs_gaussians* g, const xgs_camera* cam,
+                                  xgs_projected* out, xgs_stream_t stream) {
+    clear_error();
+    if (!g || !cam || !out) return fail(XGS_ERR_INVALID_ARG, "xgs_project: null argument");
+    if (xgs_status s = validate_camera(cam)) return s;
+    if (g->n < 0) return fail(XGS_ERR_INVALID_ARG, "xgs_project: n < 0");
+    if (g->n == 0) return XGS_OK;
+    if (!g->means || !g->log_scales || !g->quats || !g->opacity)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_project: null Gaussian array");
+    if (!out->splat || !out->radius || !out->tile_rect || !out->tiles_touched)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_project: null output array");
+    if (!aligned(g->quats, 16) || !aligned(out->splat, 16) || !aligned(out->tile_rect, 8))
+        return fail(XGS_ERR_INVALID_ARG, "xgs_project: quats/splat need 16-byte, tile_rect 8-byte alignment");
+    Grid gr = grid_of(*cam);
+    if (gr.tx > 65535 || gr.ty > 65535)
+        return fail(XGS_ERR_UNSUPPORTED, "xgs_project: more than 65535 tiles along an axis");
+    CamDev c;
+    c.fx = cam->fx; c.fy = cam->fy; c.cx = cam->cx; c.cy = cam->cy; c.near_ = cam->near_plane;
+    c.limx = kGuard * (0.5f * cam->width) / cam->fx;
+    c.limy = kGuard * (0.5f * cam->height) / cam->fy;
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) c.R[3 * r + k] = cam->viewmat[4 * r + k];
+        c.t[r] = cam->viewmat[4 * r + 3];
+    }
+    c.s = cam->stride; c.oy = cam->off_y; c.ox = cam->off_x; c.hs = gr.hs; c.ws = gr.ws;
+    int64_t blocks = (g->n + 255) / 256;
+    hipLaunchKernelGGL(project_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       g->n, g->means, g->log_scales, reinterpret_cast<const float4*>(g->quats),
+                       g->opacity, c, reinterpret_cast<float4*>(out->splat), out->radius,
+                       reinterpret_cast<uint2*>(out->tile_rect), out->tiles_touched);
+    return check_launch("xgs_project");
+}

@@ -1,0 +1,418 @@
+// a4: backward of the compositing step and of the EWA projection.
+//
+// Pixel pass: each wavefront takes an 8x8 quadrant of a tile and walks the
+// tile list back to front from the largest n_last of its pixels.  A pixel
+// recovers the transmittance in front of Gaussian k as T_k = T_{k+1}/(1-a_k),
+// starting from final_T, so nothing per (pixel, Gaussian) is stored by the
+// forward pass.  With S_k = sum_{j>k} a_j T_j (g . c_j), the derivative of
+// Eq. (rendering) is dL/da_k = T_k (g . c_k) - S_k / (1 - a_k).  The per-pixel
+// contributions of one Gaussian are summed over the wavefront by a
+// reduce-scatter (each exchange halves the number of live values per lane), so
+// one atomic instruction per Gaussian and wave carries all of its sums.
+//
+// Gaussian pass: gradients of (mean2d, conic, depth) are carried back through
+// conic = Sigma'^-1, Sigma' = J Sigma_cam J^T + 0.3 I, Sigma_cam = Rv Sigma Rv^T,
+// Sigma = (R S)(R S)^T, p = Rv mu + t (App. A).
+#include "render_common.h"
+#include "sort.h"
+
+namespace xgs {
+
+// Geometry workspace row per Gaussian (8 floats).
+enum { GW_MX = 0, GW_MY = 1, GW_A = 2, GW_B = 3, GW_C = 4, GW_DEPTH = 5, GW_STRIDE = 8 };
+
+// One halving step of the wavefront reduce-scatter: N live values, partner
+// lane = lane ^ K.  The lower lane keeps the first half, the upper lane the
+// second; an odd leftover value is summed on both and owned by the lower.
+template <int N, int K>
+__device__ __forceinline__ void rs_step(float* a, bool lower) {
+    constexpr int H = N / 2;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const float send = lower ? a[H + i] : a[i];
+        const float keep = lower ? a[i] : a[H + i];
+        a[i] = keep + __shfl_xor(send, K, 64);
+    }
+    if (N % 2) a[H] = a[2 * H] + __shfl_xor(a[2 * H], K, 64);
+}
+
+template <int N, int K>
+__device__ __forceinline__ void rs_ids(int* id, bool* own, bool lower) {
+    constexpr int H = N / 2;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        id[i] = lower ? id[i] : id[H + i];
+        own[i] = lower ? own[i] : own[H + i];
+    }
+    if (N % 2) {
+        id[H] = id[2 * H];
+        own[H] = own[2 * H] && lower;
+    }
+}
+
+constexpr int ceil2(int n) { return (n + 1) / 2; }
+
+// Reduces V values over the 64 lanes; afterwards a[0] holds the full sum of
+// value `id` (computed once by rs_layout), written by the lane with own=true.
+template <int V>
+__device__ __forceinline__ void reduce_scatter(float* a, int lane) {
+    constexpr int N1 = V, N2 = ceil2(N1), N3 = ceil2(N2), N4 = ceil2(N3), N5 = ceil2(N4), N6 = ceil2(N5);
+    rs_step<N1, 32>(a, (lane & 32) == 0);
+    rs_step<N2, 16>(a, (lane & 16) == 0);
+    rs_step<N3, 8>(a, (lane & 8) == 0);
+    rs_step<N4, 4>(a, (lane & 4) == 0);
+    rs_step<N5, 2>(a, (lane & 2) == 0);
+    rs_step<N6, 1>(a, (lane & 1) == 0);
+}
+
+template <int V>
+__device__ __forceinline__ void rs_layout(int lane, int* out_id, bool* out_own) {
+    static_assert(V <= 64, "one value per lane after the reduce-scatter");
+    int id[V];
+    bool own[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) { id[i] = i; own[i] = true; }
+    constexpr int N1 = V, N2 = ceil2(N1), N3 = ceil2(N2), N4 = ceil2(N3), N5 = ceil2(N4), N6 = ceil2(N5);
+    rs_ids<N1, 32>(id, own, (lane & 32) == 0);
+    rs_ids<N2, 16>(id, own, (lane & 16) == 0);
+    rs_ids<N3, 8>(id, own, (lane & 8) == 0);
+    rs_ids<N4, 4>(id, own, (lane & 4) == 0);
+    rs_ids<N5, 2>(id, own, (lane & 2) == 0);
+    rs_ids<N6, 1>(id, own, (lane & 1) == 0);
+    *out_id = id[0];
+    *out_own = own[0];
+}
+
+// Value layout per Gaussian: [0,3) rgb, 3 depth, [4, 4+CS) semantic, then
+// (GEO only) opacity, A, B, C, mean x, mean y.
+template <int CS, bool GEO, bool EXACT>
+__global__ void __launch_bounds__(64) render_bwd_kernel(
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const float4* __restrict__ splat, const float* __restrict__ colors,
+    const float* __restrict__ features, int csem, TileGrid g, const float* __restrict__ d_out,
+    const float* __restrict__ final_T, const int32_t* __restrict__ n_last,
+    float* __restrict__ d_colors, float* __restrict__ d_features, float* __restrict__ d_opacity,
+    float* __restrict__ geo) {
+    const QuadPix P = quad_pixel(g);
+    if (P.tile >= g.tiles) return;
+    constexpr int CH = 4 + CS;
+    constexpr int V = GEO ? CH + 6 : CS;
+    const int lane = threadIdx.x;
+    int my_id;
+    bool my_own;
+    rs_layout<V>(lane, &my_id, &my_own);
+
+    const size_t hw = (size_t)g.hs * g.ws, pix = (size_t)P.m * g.ws + P.n;
+    float gch[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) gch[c] = 0.f;
+    float T = 1.f;
+    int nl = 0;
+    if (P.inside) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gch[c] = GEO ? d_out[c * hw + pix] : 0.f;
+#pragma unroll
+        for (int c = 0; c < CS; ++c)
+            if (EXACT || c < csem) gch[4 + c] = d_out[(4 + c) * hw + pix];
+        T = final_T[pix];
+        nl = n_last[pix];
+    }
+    int jmax = nl;
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1) jmax = max(jmax, __shfl_xor(jmax, k, 64));
+    const uint32_t start = uniform(ranges[2 * P.tile]);
+    const int top = (int)uniform((uint32_t)jmax);
+    float S = 0.f;
+    for (int j = top - 1; j >= 0; --j) {
+        const uint32_t gid = uniform(vals[start + j]);
+        const float4 s0 = splat[2 * gid];
+        const float4 s1 = splat[2 * gid + 1];
+        const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
+        const bool contrib = j < nl && e.alpha >= kAlphaMin;
+        if (__ballot(contrib) == 0ull) continue;
+        const float* col = colors + 3 * (size_t)gid;
+        const int fstride = EXACT ? CS : csem;
+        const float* f = features + (size_t)gid * fstride;
+        float a[V];
+        if (contrib) {
+            const float om = 1.f - e.alpha;
+            const float Tk = T / om;
+            const float w = e.alpha * Tk;
+            float s = 0.f;
+            if (GEO) {
+                s = gch[0] * col[0] + gch[1] * col[1] + gch[2] * col[2] + gch[3] * s1.z;
+            }
+#pragma unroll
+            for (int c = 0; c < CS; ++c)
+                if (EXACT || c < csem) s += gch[4 + c] * f[c];
+            if (GEO) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c) a[c] = w * gch[c];
+                const float dalpha = Tk * s - S / om;
+                const bool clamped = !(s1.y * e.G < kAlphaMax);
+                const float dq = clamped ? 0.f : dalpha * s1.y * e.G * -0.5f;
+                a[CH + 0] = clamped ? 0.f : dalpha * e.G;
+                a[CH + 1] = dq * e.dx * e.dx;
+                a[CH + 2] = 2.f * dq * e.dx * e.dy;
+                a[CH + 3] = dq * e.dy * e.dy;
+                a[CH + 4] = -2.f * dq * (s0.z * e.dx + s0.w * e.dy);
+                a[CH + 5] = -2.f * dq * (s0.w * e.dx + s1.x * e.dy);
+            } else {
+#pragma unroll
+                for (int c = 0; c < CS; ++c) a[c] = w * gch[4 + c];
+            }
+            S += w * s;
+            T = Tk;
+        } else {
+#pragma unroll
+            for (int c = 0; c < V; ++c) a[c] = 0.f;
+        }
+        reduce_scatter<V>(a, lane);
+        if (my_own) {
+            const float v = a[0];
+            const int id = my_id;
+            float* dst = nullptr;
+            if (GEO) {
+                if (id < 3) dst = d_colors + 3 * (size_t)gid + id;
+                else if (id == 3) dst = geo + (size_t)gid * GW_STRIDE + GW_DEPTH;
+                else if (id < CH) dst = (id - 4 < csem) ? d_features + (size_t)gid * fstride + (id - 4) : nullptr;
+                else if (id == CH) dst = d_opacity + gid;
+                else if (id == CH + 1) dst = geo + (size_t)gid * GW_STRIDE + GW_A;
+                else if (id == CH + 2) dst = geo + (size_t)gid * GW_STRIDE + GW_B;
+                else if (id == CH + 3) dst = geo + (size_t)gid * GW_STRIDE + GW_C;
+                else if (id == CH + 4) dst = geo + (size_t)gid * GW_STRIDE + GW_MX;
+                else dst = geo + (size_t)gid * GW_STRIDE + GW_MY;
+            } else {
+                dst = (id < csem) ? d_features + (size_t)gid * fstride + id : nullptr;
+            }
+            if (dst) unsafeAtomicAdd(dst, v);
+        }
+    }
+}
+
+struct CamDevB {
+    float fx, fy, limx, limy, near_;
+    float R[9], t[3];
+};
+
+// Per-Gaussian chain rule from (mean2d, conic, depth) to (mean, log-scale,
+// quaternion); the forward quantities are recomputed from the parameters.
+__global__ void __launch_bounds__(256) project_bwd_kernel(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const int32_t* __restrict__ radius,
+    const float4* __restrict__ splat, const float* __restrict__ geo, CamDevB c,
+    float* __restrict__ d_means, float* __restrict__ d_ls, float4* __restrict__ d_quats) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gm[3] = {0.f, 0.f, 0.f}, gl[3] = {0.f, 0.f, 0.f};
+    float4 gq = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (radius[i] > 0) {
+        const float* gw = geo + (size_t)i * GW_STRIDE;
+        const float gmx = gw[GW_MX], gmy = gw[GW_MY];
+        const float gA = gw[GW_A], gB = gw[GW_B], gC = gw[GW_C], gd = gw[GW_DEPTH];
+        const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+        const float px = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
+        const float py = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
+        const float pz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
+        float4 q = quats[i];
+        const float qn = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+        const float inv = 1.f / qn;
+        const float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
+        float R[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
+                         {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
+                         {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+        const float s[3] = {__expf(log_scales[3 * i]), __expf(log_scales[3 * i + 1]),
+                            __expf(log_scales[3 * i + 2])};
+        float M[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) M[r][k] = R[r][k] * s[k];
+        // Sigma_cam = (Rv M)(Rv M)^T
+        float TM[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k)
+                TM[r][k] = c.R[3 * r] * M[0][k] + c.R[3 * r + 1] * M[1][k] + c.R[3 * r + 2] * M[2][k];
+        float Sc[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) Sc[r][k] = TM[r][0] * TM[k][0] + TM[r][1] * TM[k][1] + TM[r][2] * TM[k][2];
+        const float iz = 1.f / pz;
+        const float u = px * iz, v = py * iz;
+        const bool clx = u < -c.limx || u > c.limx, cly = v < -c.limy || v > c.limy;
+        const float tx = fminf(fmaxf(u, -c.limx), c.limx) * pz;
+        const float ty = fminf(fmaxf(v, -c.limy), c.limy) * pz;
+        const float J[2][3] = {{c.fx * iz, 0.f, -c.fx * tx * iz * iz}, {0.f, c.fy * iz, -c.fy * ty * iz * iz}};
+        // conic = (A, B, C) from the splat record; dSigma' = -K Ghat K
+        const float4 s0 = splat[2 * i], s1 = splat[2 * i + 1];
+        const float K00 = s0.z, K01 = s0.w, K11 = s1.x;
+        const float G00 = gA, G01 = 0.5f * gB, G11 = gC;
+        const float KG00 = K00 * G00 + K01 * G01, KG01 = K00 * G01 + K01 * G11;
+        const float KG10 = K01 * G00 + K11 * G01, KG11 = K01 * G01 + K11 * G11;
+        const float dS00 = -(KG00 * K00 + KG01 * K01);
+        const float dS01 = -(KG00 * K01 + KG01 * K11);
+        const float dS11 = -(KG10 * K01 + KG11 * K11);
+        const float dS[2][2] = {{dS00, dS01}, {dS01, dS11}};
+        // dSc = J^T dS J ; dJ = 2 dS J Sc
+        float dSc[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) {
+                float acc = 0.f;
+                for (int a = 0; a < 2; ++a)
+                    for (int bb = 0; bb < 2; ++bb) acc += J[a][r] * dS[a][bb] * J[bb][k];
+                dSc[r][k] = acc;
+            }
+        float JSc[2][3];
+        for (int r = 0; r < 2; ++r)
+            for (int k = 0; k < 3; ++k) JSc[r][k] = J[r][0] * Sc[0][k] + J[r][1] * Sc[1][k] + J[r][2] * Sc[2][k];
+        float dJ[2][3];
+        for (int r = 0; r < 2; ++r)
+            for (int k = 0; k < 3; ++k) dJ[r][k] = 2.f * (dS[r][0] * JSc[0][k] + dS[r][1] * JSc[1][k]);
+        // dSigma = Rv^T dSc Rv
+        float tmp[3][3], dSig[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k)
+                tmp[r][k] = c.R[r] * dSc[0][k] + c.R[3 + r] * dSc[1][k] + c.R[6 + r] * dSc[2][k];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k)
+                dSig[r][k] = tmp[r][0] * c.R[k] + tmp[r][1] * c.R[3 + k] + tmp[r][2] * c.R[6 + k];
+        // dM = 2 dSig M ; dR = dM diag(s) ; ds = diag(R^T dM)
+        float dR[3][3];
+        for (int k = 0; k < 3; ++k) {
+            float ds = 0.f;
+            for (int r = 0; r < 3; ++r) {
+                const float dM = 2.f * (dSig[r][0] * M[0][k] + dSig[r][1] * M[1][k] + dSig[r][2] * M[2][k]);
+                ds += dM * R[r][k];
+                dR[r][k] = dM * s[k];
+            }
+            gl[k] = ds * s[k];
+        }
+        float g0 = 2.f * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
+        float g1 = 2.f * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.f * x * dR[1][1] - w * dR[1][2] +
+                          z * dR[2][0] + w * dR[2][1] - 2.f * x * dR[2][2]);
+        float g2 = 2.f * (-2.f * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] -
+                          w * dR[2][0] + z * dR[2][1] - 2.f * y * dR[2][2]);
+        float g3 = 2.f * (-2.f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.f * z * dR[1][1] +
+                          y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+        const float dot = w * g0 + x * g1 + y * g2 + z * g3;
+        gq = make_float4((g0 - w * dot) * inv, (g1 - x * dot) * inv, (g2 - y * dot) * inv, (g3 - z * dot) * inv);
+        // J(p), mean2d(p), depth(p) -> p -> mu
+        const float iz2 = iz * iz, iz3 = iz2 * iz;
+        const float dtx_dpx = clx ? 0.f : 1.f, dtx_dpz = clx ? tx * iz : 0.f;
+        const float dty_dpy = cly ? 0.f : 1.f, dty_dpz = cly ? ty * iz : 0.f;
+        float dpx = dJ[0][2] * (-c.fx * iz2) * dtx_dpx + gmx * c.fx * iz;
+        float dpy = dJ[1][2] * (-c.fy * iz2) * dty_dpy + gmy * c.fy * iz;
+        float dpz = dJ[0][0] * (-c.fx * iz2) + dJ[1][1] * (-c.fy * iz2) +
+                    dJ[0][2] * (-c.fx * iz2 * dtx_dpz + 2.f * c.fx * tx * iz3) +
+                    dJ[1][2] * (-c.fy * iz2 * dty_dpz + 2.f * c.fy * ty * iz3) -
+                    gmx * c.fx * px * iz2 - gmy * c.fy * py * iz2 + gd;
+        for (int k = 0; k < 3; ++k) gm[k] = c.R[k] * dpx + c.R[3 + k] * dpy + c.R[6 + k] * dpz;
+    }
+    d_means[3 * i] = gm[0]; d_means[3 * i + 1] = gm[1]; d_means[3 * i + 2] = gm[2];
+    d_ls[3 * i] = gl[0]; d_ls[3 * i + 1] = gl[1]; d_ls[3 * i + 2] = gl[2];
+    d_quats[i] = gq;
+}
+
+template <int CS, bool GEO, bool EXACT = true>
+static void launch_bwd(const xgs_gaussians* g, const xgs_projected* p, const xgs_binning* b,
+                       const TileGrid& tg, const float* d_out, const float* final_T,
+                       const int32_t* n_last, xgs_gaussians_grad* gr, float* geo, hipStream_t st) {
+    hipLaunchKernelGGL((render_bwd_kernel<CS, GEO, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
+                       b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
+                       g->c_sem, tg, d_out, final_T, n_last, gr->colors, gr->features, gr->opacity, geo);
+}
+
+template <bool GEO>
+static void dispatch_bwd(const xgs_gaussians* g, const xgs_projected* p, const xgs_binning* b,
+                         const TileGrid& tg, const float* d_out, const float* final_T,
+                         const int32_t* n_last, xgs_gaussians_grad* gr, float* geo, hipStream_t st) {
+    const int cs = g->c_sem;
+    if (!GEO && cs == 0) return;
+    switch (cs) {
+#define XGS_BWD_CASE(n) case n: launch_bwd<n, GEO>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st); return;
+        XGS_BWD_CASE(1) XGS_BWD_CASE(2) XGS_BWD_CASE(3) XGS_BWD_CASE(4) XGS_BWD_CASE(8)
+        XGS_BWD_CASE(12) XGS_BWD_CASE(16) XGS_BWD_CASE(24) XGS_BWD_CASE(32) XGS_BWD_CASE(48)
+#undef XGS_BWD_CASE
+        default: break;
+    }
+    if constexpr (GEO) {
+        if (cs == 0) launch_bwd<0, true>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
+        else if (cs <= 16) launch_bwd<16, true, false>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
+        else if (cs <= 32) launch_bwd<32, true, false>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
+        else launch_bwd<54, true, false>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
+    } else {
+        if (cs == 64) launch_bwd<64, false>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
+        else if (cs <= 16) launch_bwd<16, false, false>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
+        else if (cs <= 32) launch_bwd<32, false, false>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
+        else launch_bwd<64, false, false>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
+    }
+}
+
+}  // namespace xgs
+
+using namespace xgs;
+
+extern "C" size_t xgs_render_bwd_workspace(int64_t n) {
+    Carve c(nullptr);
+    c.take<float>((size_t)(n > 0 ? n : 1) * GW_STRIDE);
+    return c.total();
+}
+
+extern "C" xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected* p,
+                                     const xgs_binning* b, const xgs_camera* cam, const float* d_out,
+                                     const float* final_T, const int32_t* n_last, int32_t flags,
+                                     xgs_gaussians_grad* gr, void* ws, size_t ws_bytes,
+                                     xgs_stream_t stream) {
+    clear_error();
+    if (!g || !p || !b || !cam || !gr) return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: null argument");
+    if (xgs_status s = validate_camera(cam)) return s;
+    if (flags != XGS_BWD_ALL && flags != XGS_BWD_FEATURES_ONLY)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: unknown flags");
+    const bool geo_on = flags == XGS_BWD_ALL;
+    if (g->c_sem < 0 || g->c_sem > XGS_MAX_C_SEM)
+        return fail(XGS_ERR_UNSUPPORTED, "xgs_render_bwd: c_sem must be in [0, 64]");
+    if (geo_on && g->c_sem > 54)
+        return fail(XGS_ERR_UNSUPPORTED, "xgs_render_bwd: c_sem <= 54 (4 + c_sem + 6 sums per lane)");
+    if (gr->n != g->n || gr->c_sem != g->c_sem)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: gradient shapes differ from the Gaussians");
+    if (!d_out || !final_T || !n_last) return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: null image buffer");
+    if (g->n > 0) {
+        if (!g->colors || (g->c_sem > 0 && !g->features) || !p->splat || !p->radius)
+            return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: null Gaussian array");
+        if (g->c_sem > 0 && !gr->features)
+            return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: null feature gradient");
+        if (geo_on && (!gr->means || !gr->log_scales || !gr->quats || !gr->opacity || !gr->colors ||
+                       !g->means || !g->log_scales || !g->quats))
+            return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: null gradient array");
+        if (geo_on && !aligned(gr->quats, 16))
+            return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: quats gradient must be 16-byte aligned");
+    }
+    if (!aligned(ws, 256)) return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: workspace must be 256-byte aligned");
+    if (!ws || ws_bytes < xgs_render_bwd_workspace(g->n))
+        return fail(XGS_ERR_CAPACITY, "xgs_render_bwd: workspace too small");
+    if (g->n == 0) return XGS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    float* geo = static_cast<float*>(ws);
+    xgs_status s;
+    if (g->c_sem > 0 && (s = fill_f32(gr->features, g->n * g->c_sem, 0.f, st))) return s;
+    TileGrid tg = tile_grid(*cam);
+    if (geo_on) {
+        if ((s = fill_f32(gr->colors, 3 * g->n, 0.f, st))) return s;
+        if ((s = fill_f32(gr->opacity, g->n, 0.f, st))) return s;
+        if ((s = fill_f32(geo, GW_STRIDE * g->n, 0.f, st))) return s;
+        dispatch_bwd<true>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
+        if ((s = check_launch("xgs_render_bwd pixels"))) return s;
+        CamDevB c;
+        c.fx = cam->fx; c.fy = cam->fy; c.near_ = cam->near_plane;
+        c.limx = kGuard * (0.5f * cam->width) / cam->fx;
+        c.limy = kGuard * (0.5f * cam->height) / cam->fy;
+        for (int r = 0; r < 3; ++r) {
+            for (int k = 0; k < 3; ++k) c.R[3 * r + k] = cam->viewmat[4 * r + k];
+            c.t[r] = cam->viewmat[4 * r + 3];
+        }
+        hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)((g->n + 255) / 256)), dim3(256), 0, st, g->n,
+                           g->means, g->log_scales, reinterpret_cast<const float4*>(g->quats), p->radius,
+                           reinterpret_cast<const float4*>(p->splat), geo, c, gr->means, gr->log_scales,
+                           reinterpret_cast<float4*>(gr->quats));
+        return check_launch("xgs_render_bwd projection");
+    }
+    dispatch_bwd<false>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
+    return check_launch("xgs_render_bwd features");
+}

@@ -1,0 +1,108 @@
+// a3: front-to-back alpha compositing of RGB, depth and semantic channels,
+// Eq. (rendering) with the feature and depth substitutions (Sec. 3.1, App. B),
+// evaluated only at the sampled grid pixels (App. D): the rasterizer never
+// forms the dense map when stride > 1.
+#include "render_common.h"
+
+namespace xgs {
+
+// CS: compile-time semantic channel count.  EXACT: csem == CS, so feature
+// rows have a compile-time stride and merge into wide scalar loads; otherwise
+// CS only bounds csem and channels >= csem are neither read nor written.
+template <int CS, bool EXACT>
+__global__ void __launch_bounds__(64) render_fwd_kernel(
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const float4* __restrict__ splat, const float* __restrict__ colors,
+    const float* __restrict__ features, int csem, TileGrid g, float* __restrict__ out,
+    float* __restrict__ final_T, int32_t* __restrict__ n_last) {
+    const QuadPix P = quad_pixel(g);
+    if (P.tile >= g.tiles) return;
+    constexpr int CH = 4 + CS;
+    float acc[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) acc[c] = 0.f;
+    float T = 1.f;
+    uint32_t last = 0;
+    bool done = !P.inside;
+    const uint32_t start = uniform(ranges[2 * P.tile]);
+    const uint32_t end = uniform(ranges[2 * P.tile + 1]);
+    for (uint32_t j = start; j < end; ++j) {
+        if (__ballot(!done) == 0ull) break;
+        const uint32_t gid = uniform(vals[j]);
+        const float4 s0 = splat[2 * gid];
+        const float4 s1 = splat[2 * gid + 1];
+        const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
+        bool contrib = !done && e.alpha >= kAlphaMin;
+        if (__ballot(contrib) == 0ull) continue;
+        const float Tn = T * (1.f - e.alpha);
+        if (contrib && Tn < kTStop) {
+            done = true;
+            contrib = false;
+        }
+        if (contrib) {
+            const float w = e.alpha * T;
+            const float* col = colors + 3 * (size_t)gid;
+            acc[0] += w * col[0];
+            acc[1] += w * col[1];
+            acc[2] += w * col[2];
+            acc[3] += w * s1.z;
+            const float* f = features + (size_t)gid * (EXACT ? CS : csem);
+#pragma unroll
+            for (int c = 0; c < CS; ++c)
+                if (EXACT || c < csem) acc[4 + c] += w * f[c];
+            T = Tn;
+            last = j - start + 1;
+        }
+    }
+    if (!P.inside) return;
+    const size_t hw = (size_t)g.hs * g.ws, pix = (size_t)P.m * g.ws + P.n;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[c * hw + pix] = acc[c];
+#pragma unroll
+    for (int c = 0; c < CS; ++c)
+        if (EXACT || c < csem) out[(4 + c) * hw + pix] = acc[4 + c];
+    final_T[pix] = T;
+    n_last[pix] = (int32_t)last;
+}
+
+template <int CS, bool EXACT = true>
+static void launch_fwd(const xgs_gaussians* g, const xgs_projected* p, const xgs_binning* b,
+                       const TileGrid& tg, float* out, float* final_T, int32_t* n_last,
+                       hipStream_t st) {
+    hipLaunchKernelGGL((render_fwd_kernel<CS, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
+                       b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
+                       g->c_sem, tg, out, final_T, n_last);
+}
+
+}  // namespace xgs
+
+using namespace xgs;
+
+extern "C" xgs_status xgs_render_fwd(const xgs_gaussians* g, const xgs_projected* p,
+                                     const xgs_binning* b, const xgs_camera* cam, float* out,
+                                     float* final_T, int32_t* n_last, xgs_stream_t stream) {
+    clear_error();
+    if (!g || !p || !b || !cam) return fail(XGS_ERR_INVALID_ARG, "xgs_render_fwd: null argument");
+    if (xgs_status s = validate_camera(cam)) return s;
+    if (!out || !final_T || !n_last) return fail(XGS_ERR_INVALID_ARG, "xgs_render_fwd: null output");
+    if (g->c_sem < 0 || g->c_sem > XGS_MAX_C_SEM)
+        return fail(XGS_ERR_UNSUPPORTED, "xgs_render_fwd: c_sem must be in [0, 64]");
+    if (g->n > 0 && (!g->colors || (g->c_sem > 0 && !g->features) || !p->splat))
+        return fail(XGS_ERR_INVALID_ARG, "xgs_render_fwd: null Gaussian array");
+    if (!b->ranges || !b->vals) return fail(XGS_ERR_INVALID_ARG, "xgs_render_fwd: null binning array");
+    if (!aligned(p->splat, 16)) return fail(XGS_ERR_INVALID_ARG, "xgs_render_fwd: splat must be 16-byte aligned");
+    TileGrid tg = tile_grid(*cam);
+    hipStream_t st = (hipStream_t)stream;
+    switch (g->c_sem) {
+#define XGS_FWD_CASE(n) case n: launch_fwd<n>(g, p, b, tg, out, final_T, n_last, st); break;
+        XGS_FWD_CASE(0) XGS_FWD_CASE(1) XGS_FWD_CASE(2) XGS_FWD_CASE(3) XGS_FWD_CASE(4)
+        XGS_FWD_CASE(8) XGS_FWD_CASE(12) XGS_FWD_CASE(16) XGS_FWD_CASE(24) XGS_FWD_CASE(32)
+        XGS_FWD_CASE(48) XGS_FWD_CASE(64)
+#undef XGS_FWD_CASE
+        default:
+            if (g->c_sem <= 16) launch_fwd<16, false>(g, p, b, tg, out, final_T, n_last, st);
+            else if (g->c_sem <= 32) launch_fwd<32, false>(g, p, b, tg, out, final_T, n_last, st);
+            else launch_fwd<64, false>(g, p, b, tg, out, final_T, n_last, st);
+    }
+    return check_launch("xgs_render_fwd");
+}

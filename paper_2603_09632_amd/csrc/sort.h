@@ -1,0 +1,43 @@
+// Device-wide exclusive scan and stable LSD radix sort of (u64 key, u32 value)
+// pairs whose count lives in device memory (no host synchronisation).
+#pragma once
+#include "common.h"
+
+namespace xgs {
+
+constexpr int kScanItems = 2048;   // elements per scan block (256 threads x 8)
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;    // rounds of 256 items per sort block
+constexpr int kSortItems = kSortThreads * kSortRounds;
+
+inline int64_t scan_blocks(int64_t n) { return (n + kScanItems - 1) / kScanItems; }
+inline int64_t sort_blocks(int64_t cap) { return (cap + kSortItems - 1) / kSortItems; }
+
+// Exclusive scan of in[0..n) (u32) into out (u64); *total = sum, and when
+// cap >= 0: *count = sum (0 if sum > cap), *status = sum > cap.
+// partials must hold scan_blocks(n) + 1 entries.
+xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint64_t* partials,
+                              int64_t* total, int64_t cap, int64_t* count, int32_t* status,
+                              hipStream_t stream);
+
+// Stable LSD radix sort of the first *count pairs (count <= cap) on key bits
+// [0, key_bits).  Pairs start in (k0, v0); the sorted result is left in
+// (k0, v0) if the number of 8-bit passes is even, otherwise in (k1, v1);
+// *in_first reports which.  hist must hold 256 * sort_blocks(cap) u32.
+int radix_passes(int key_bits);
+xgs_status radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                      const int64_t* count, int64_t cap, int key_bits, uint32_t* hist,
+                      hipStream_t stream);
+
+// Fills n u32 with a value (used instead of hipMemsetAsync so that the calls
+// stay safe to record into graphs).
+xgs_status fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
+xgs_status fill_f32(float* p, int64_t n, float v, hipStream_t stream);
+
+// ranges[2 s] = first, ranges[2 s + 1] = last + 1 position of segment
+// s = keys[i] >> shift among the first *count sorted keys; segments absent
+// from the keys keep whatever the caller filled in.
+xgs_status segment_ranges(const uint64_t* keys, const int64_t* count, int64_t cap, int shift,
+                          uint32_t* ranges, hipStream_t stream);
+
+}  // namespace xgs

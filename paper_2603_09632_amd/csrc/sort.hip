@@ -1,0 +1,268 @@
+// Scan and radix sort used by the binning step (and by the VQ EMA update to
+// group rows by codeword).  All sizes that depend on data are read from device
+// memory; grids are sized by the caller's capacity and idle blocks return.
+#include "sort.h"
+
+namespace xgs {
+
+// ------------------------------------------------------------------ fill
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+xgs_status fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream) {
+    if (n <= 0) return XGS_OK;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
+    return check_launch("fill");
+}
+
+xgs_status fill_f32(float* p, int64_t n, float v, hipStream_t stream) {
+    union { float f; uint32_t u; } c;
+    c.f = v;
+    return fill_u32(reinterpret_cast<uint32_t*>(p), n, c.u, stream);
+}
+
+// ------------------------------------------------------------------ scan
+// Block-wide inclusive scan of one u64 per thread (256 threads).
+__device__ __forceinline__ uint64_t block_incl_scan_256(uint64_t v, uint64_t* sh) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    if (lane == 63) sh[w] = v;
+    __syncthreads();
+    uint64_t add = 0;
+    for (int k = 0; k < w; ++k) add += sh[k];
+    __syncthreads();
+    return v + add;
+}
+
+__global__ void __launch_bounds__(256) scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                         uint64_t* __restrict__ partials) {
+    __shared__ uint64_t sh[4];
+    int64_t base = (int64_t)blockIdx.x * kScanItems;
+    uint64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems / 256; ++r) {
+        int64_t i = base + r * 256 + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint64_t incl = block_incl_scan_256(s, sh);
+    if (threadIdx.x == 255) partials[blockIdx.x] = incl;
+}
+
+// One block: exclusive scan of the block partials in place, then the total.
+__global__ void __launch_bounds__(256) scan_partials_kernel(uint64_t* partials, int64_t nb,
+                                                           int64_t* total, int64_t cap,
+                                                           int64_t* count, int32_t* status) {
+    __shared__ uint64_t sh[4];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+        int64_t i = b0 + threadIdx.x;
+        uint64_t v = i < nb ? partials[i] : 0;
+        uint64_t incl = block_incl_scan_256(v, sh);
+        uint64_t c = carry;
+        if (i < nb) partials[i] = c + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 255) carry = c + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        uint64_t tot = carry;
+        partials[nb] = tot;
+        if (total) *total = (int64_t)tot;
+        if (cap >= 0) {
+            // on overflow nothing is sorted: the lists are empty and status says why
+            *count = (int64_t)(tot > (uint64_t)cap ? 0 : tot);
+            *status = tot > (uint64_t)cap ? 1 : 0;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) scan_apply_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                        const uint64_t* __restrict__ partials,
+                                                        uint64_t* __restrict__ out) {
+    __shared__ uint64_t sh[4];
+    constexpr int per = kScanItems / 256;  // consecutive items per thread
+    int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * per;
+    uint32_t v[per];
+    uint64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < per; ++r) {
+        int64_t i = base + r;
+        v[r] = i < n ? in[i] : 0u;
+        s += v[r];
+    }
+    uint64_t incl = block_incl_scan_256(s, sh);
+    uint64_t run = partials[blockIdx.x] + incl - s;
+#pragma unroll
+    for (int r = 0; r < per; ++r) {
+        int64_t i = base + r;
+        if (i < n) out[i] = run;
+        run += v[r];
+    }
+}
+
+xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint64_t* partials,
+                              int64_t* total, int64_t cap, int64_t* count, int32_t* status,
+                              hipStream_t stream) {
+    int64_t nb = scan_blocks(n);
+    if (nb > 0)
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, stream, in, n, partials);
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(256), 0, stream, partials, nb, total, cap,
+                       count, status);
+    if (nb > 0)
+        hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(256), 0, stream, in, n, partials, out);
+    return check_launch("scan");
+}
+
+// ------------------------------------------------------------ radix sort
+__global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t* __restrict__ keys,
+                                                                 const int64_t* __restrict__ count,
+                                                                 int shift, uint32_t mask,
+                                                                 uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    const int64_t m = *count;
+    const int64_t base = (int64_t)blockIdx.x * kSortItems;
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    if (base < m) {
+#pragma unroll 4
+        for (int r = 0; r < kSortRounds; ++r) {
+            int64_t i = base + r * kSortThreads + threadIdx.x;
+            if (i < m) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// One block of 1024 threads: exclusive scan of the digit-major histogram.
+__global__ void __launch_bounds__(1024) radix_scan_kernel(uint32_t* hist, int64_t len) {
+    __shared__ uint32_t sh[1024];
+    const int t = threadIdx.x;
+    int64_t per = (len + 1023) / 1024;
+    int64_t b = t * per, e = b + per < len ? b + per : len;
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += hist[i];
+    sh[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        uint32_t o = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += o;
+        __syncthreads();
+    }
+    uint32_t run = sh[t] - s;
+    for (int64_t i = b; i < e; ++i) {
+        uint32_t v = hist[i];
+        hist[i] = run;
+        run += v;
+    }
+}
+
+// Stable scatter.  Items are ranked in block order (round, wave, lane): a
+// lane's rank among equal digits in its wave comes from 8 ballots, the
+// per-wave counts are prefixed through LDS, and a running per-digit base
+// carries the order across rounds.
+__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const int64_t* __restrict__ count, int shift, uint32_t mask,
+    int nbits, const uint32_t* __restrict__ hist) {
+    __shared__ uint32_t goff[256];
+    __shared__ uint32_t wcnt[4][256];
+    const int64_t m = *count;
+    const int64_t base = (int64_t)blockIdx.x * kSortItems;
+    if (base >= m) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    goff[t] = hist[(int64_t)t * gridDim.x + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kSortRounds; ++r) {
+        int64_t i = base + r * kSortThreads + t;
+        if (base + r * kSortThreads >= m) break;  // uniform across the block
+        bool valid = i < m;
+        uint64_t key = valid ? kin[i] : 0ull;
+        uint32_t val = valid ? vin[i] : 0u;
+        uint32_t d = (uint32_t)(key >> shift) & mask;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            uint64_t bm = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bm : ~bm;
+        }
+        uint32_t rank = __popcll(peers & lt);
+        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+        __syncthreads();
+        // thread t turns the 4 wave counts of digit t into exclusive offsets
+        uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+        uint32_t g = goff[t];
+        __syncthreads();
+        wcnt[0][t] = g;
+        wcnt[1][t] = g + c0;
+        wcnt[2][t] = g + c0 + c1;
+        wcnt[3][t] = g + c0 + c1 + c2;
+        goff[t] = g + c0 + c1 + c2 + c3;
+        __syncthreads();
+        if (valid) {
+            uint32_t dst = wcnt[w][d] + rank;
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+        __syncthreads();
+    }
+}
+
+int radix_passes(int key_bits) { return (key_bits + 7) / 8; }
+
+xgs_status radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const int64_t* count,
+                      int64_t cap, int key_bits, uint32_t* hist, hipStream_t stream) {
+    int64_t nb = sort_blocks(cap);
+    if (nb == 0) return XGS_OK;
+    int passes = radix_passes(key_bits);
+    uint64_t* ki = k0; uint32_t* vi = v0; uint64_t* ko = k1; uint32_t* vo = v1;
+    for (int p = 0; p < passes; ++p) {
+        int shift = 8 * p;
+        int nbits = key_bits - shift < 8 ? key_bits - shift : 8;
+        uint32_t mask = (1u << nbits) - 1u;
+        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, ki,
+                           count, shift, mask, hist);
+        hipLaunchKernelGGL(radix_scan_kernel, dim3(1), dim3(1024), 0, stream, hist, nb * 256);
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream,
+                           ki, vi, ko, vo, count, shift, mask, nbits, hist);
+        uint64_t* tk = ki; ki = ko; ko = tk;
+        uint32_t* tv = vi; vi = vo; vo = tv;
+    }
+    return check_launch("radix_sort");
+}
+
+// ---------------------------------------------------------------- ranges
+__global__ void ranges_kernel(const uint64_t* __restrict__ keys, const int64_t* __restrict__ count,
+                              int shift, uint32_t* __restrict__ ranges) {
+    const int64_t m = *count;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    uint64_t s = keys[i] >> shift;
+    if (i == 0 || (keys[i - 1] >> shift) != s) ranges[2 * s] = (uint32_t)i;
+    if (i == m - 1 || (keys[i + 1] >> shift) != s) ranges[2 * s + 1] = (uint32_t)(i + 1);
+}
+
+xgs_status segment_ranges(const uint64_t* keys, const int64_t* count, int64_t cap, int shift,
+                          uint32_t* ranges, hipStream_t stream) {
+    if (cap <= 0) return XGS_OK;
+    int64_t blocks = (cap + 255) / 256;
+    hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, keys, count, shift,
+                       ranges);
+    return check_launch("ranges");
+}
+
+}  // namespace xgs

@@ -1,0 +1,112 @@
+// a2: binning of projected splats into 16x16 tiles and per-tile depth sort.
+// Keys are (tile_id << 32) | bits(depth): camera depths are positive, and
+// positive IEEE binary32 values order like their bit patterns.  Keys are
+// emitted in Gaussian order and sorted with a stable LSD radix sort, so equal
+// keys keep ascending Gaussian index.
+#include "sort.h"
+
+namespace xgs {
+
+__global__ void __launch_bounds__(256) emit_keys_kernel(
+    int64_t n, const uint2* __restrict__ tile_rect, const uint32_t* __restrict__ touched,
+    const float4* __restrict__ splat, const uint64_t* __restrict__ offsets, int64_t cap, int tiles_x,
+    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t cnt = touched[i];
+    if (cnt == 0) return;
+    uint64_t off = offsets[i];
+    if (off + cnt > (uint64_t)cap) return;  // overflow: status already set by the scan
+    uint2 r = tile_rect[i];
+    uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+    uint32_t dbits = __float_as_uint(splat[2 * i + 1].z);
+    for (uint32_t y = y0; y < y1; ++y)
+        for (uint32_t x = x0; x < x1; ++x) {
+            uint64_t tile = (uint64_t)y * (uint32_t)tiles_x + x;
+            keys[off] = (tile << 32) | dbits;
+            vals[off] = (uint32_t)i;
+            ++off;
+        }
+}
+
+struct SortWs {
+    uint64_t* offsets;
+    uint64_t* partials;
+    uint64_t* keys_alt;
+    uint32_t* vals_alt;
+    uint32_t* hist;
+    int64_t* total;
+};
+
+static SortWs carve_sort(void* base, int64_t n, int64_t cap, size_t* bytes) {
+    Carve c(base);
+    SortWs w;
+    w.offsets = c.take<uint64_t>(n > 0 ? n : 1);
+    w.partials = c.take<uint64_t>(scan_blocks(n) + 1);
+    w.keys_alt = c.take<uint64_t>(cap > 0 ? cap : 1);
+    w.vals_alt = c.take<uint32_t>(cap > 0 ? cap : 1);
+    w.hist = c.take<uint32_t>(256 * (sort_blocks(cap) > 0 ? sort_blocks(cap) : 1));
+    w.total = c.take<int64_t>(1);
+    *bytes = c.total();
+    return w;
+}
+
+static int tile_bits(int64_t tiles) {
+    int b = 0;
+    while ((int64_t(1) << b) < tiles) ++b;
+    return b;
+}
+
+}  // namespace xgs
+
+using namespace xgs;
+
+extern "C" size_t xgs_tile_sort_workspace(int64_t n, int64_t max_instances, int32_t num_tiles) {
+    (void)num_tiles;
+    size_t bytes = 0;
+    carve_sort(nullptr, n < 0 ? 0 : n, max_instances < 0 ? 0 : max_instances, &bytes);
+    return bytes;
+}
+
+extern "C" xgs_status xgs_tile_sort(const xgs_projected* p, const xgs_camera* cam, int64_t n,
+                                    void* ws, size_t ws_bytes, xgs_binning* b, xgs_stream_t stream) {
+    clear_error();
+    if (!p || !cam || !b) return fail(XGS_ERR_INVALID_ARG, "xgs_tile_sort: null argument");
+    if (xgs_status s = validate_camera(cam)) return s;
+    if (n < 0 || b->max_instances < 0)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_tile_sort: negative size");
+    if (b->max_instances >= (int64_t(1) << 32))
+        return fail(XGS_ERR_UNSUPPORTED, "xgs_tile_sort: max_instances must be below 2^32");
+    if (!b->keys || !b->vals || !b->ranges || !b->num_instances || !b->status)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_tile_sort: null binning array");
+    if (n > 0 && (!p->splat || !p->tile_rect || !p->tiles_touched))
+        return fail(XGS_ERR_INVALID_ARG, "xgs_tile_sort: null projected array");
+    if (!aligned(ws, 256)) return fail(XGS_ERR_INVALID_ARG, "xgs_tile_sort: workspace must be 256-byte aligned");
+    size_t need = 0;
+    SortWs w = carve_sort(ws, n, b->max_instances, &need);
+    if (ws_bytes < need || !ws)
+        return fail(XGS_ERR_CAPACITY, "xgs_tile_sort: workspace too small (need " + std::to_string(need) + " bytes)");
+    hipStream_t st = (hipStream_t)stream;
+    Grid g = grid_of(*cam);
+    int64_t tiles = (int64_t)g.tx * g.ty;
+    const int64_t cap = b->max_instances;
+    xgs_status s = fill_u32(b->ranges, 2 * tiles, 0u, st);
+    if (s) return s;
+    s = exclusive_scan_u32(p->tiles_touched, n, w.offsets, w.partials, w.total, cap, b->num_instances,
+                           b->status, st);
+    if (s) return s;
+    int bits = 32 + tile_bits(tiles);
+    bool even = radix_passes(bits) % 2 == 0;
+    uint64_t* k0 = even ? b->keys : w.keys_alt;
+    uint32_t* v0 = even ? b->vals : w.vals_alt;
+    uint64_t* k1 = even ? w.keys_alt : b->keys;
+    uint32_t* v1 = even ? w.vals_alt : b->vals;
+    if (n > 0) {
+        hipLaunchKernelGGL(emit_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                           reinterpret_cast<const uint2*>(p->tile_rect), p->tiles_touched,
+                           reinterpret_cast<const float4*>(p->splat), w.offsets, cap, g.tx, k0, v0);
+        if ((s = check_launch("xgs_tile_sort emit"))) return s;
+    }
+    if ((s = radix_sort(k0, v0, k1, v1, b->num_instances, cap, bits, w.hist, st))) return s;
+    return segment_ranges(b->keys, b->num_instances, cap, 32, b->ranges, st);
+}

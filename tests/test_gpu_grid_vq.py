@@ -1,0 +1,169 @@
+"""GPU parity of grid-sampled targets (a5), VQ assignment (a6) and the EMA
+update (a7) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import np_, rel_max, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def xgs():
+    return require_gpu()
+
+
+def t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# ------------------------------------------------------------------ a5
+@pytest.mark.parametrize("H,W,Hf,Wf,D,stride,oy,ox", [
+    (480, 640, 30, 40, 512, 1, 0, 0),     # the mapping-scale target map
+    (96, 128, 7, 9, 13, 3, 2, 1),         # ragged: H_s*W_s not a multiple of 4
+    (50, 70, 13, 5, 6, 4, 3, 3),          # padded rows/columns at a large offset
+    (17, 1, 4, 1, 3, 2, 1, 0),            # degenerate width
+])
+def test_grid_sample(xgs, H, W, Hf, Wf, D, stride, oy, ox):
+    P = synth.feature_map(D, Hf, Wf, seed=H + W)
+    for mode in (xgs.GRID_BILINEAR, xgs.GRID_NEAREST):
+        G, V = xgs.xgs_grid_sample(t(P), H, W, stride, oy, ox, mode)
+        torch.cuda.synchronize()
+        Gr, Vr = oracle.grid_sample(P, H, W, stride, oy, ox, mode)
+        np.testing.assert_array_equal(np_(V), Vr)
+        if mode == xgs.GRID_NEAREST:
+            np.testing.assert_array_equal(np_(G), Gr)  # a copy: bit-exact
+        else:
+            assert rel_max(np_(G), Gr) < 1e-6
+
+
+def test_grid_sample_affine_exact(xgs):
+    P = synth.affine_feature_map(5, 9, 17)
+    G, _ = xgs.xgs_grid_sample(t(P), 65, 65)
+    Gr, _ = oracle.grid_sample(P, 65, 65)
+    np.testing.assert_array_equal(np_(G), Gr)
+
+
+# ------------------------------------------------------------------ a6
+def agreement(idx, ref_idx, d1, d2, tie_rel=1e-6):
+    raw = float((idx == ref_idx).mean())
+    tie = (d2 - d1) <= tie_rel * np.maximum(d1, 1e-30)
+    adj = float(((idx == ref_idx) | tie).mean())
+    return raw, adj
+
+
+def vq_case(n, d, k, clusters, seed=2):
+    X = synth.vq_mixture(n, d, clusters, seed=seed)
+    E = synth.vq_codebook(k, d, clusters, seed=seed + 1, centre_seed=seed)
+    return X, E
+
+
+@pytest.mark.parametrize("n,d,k", [(12_288, 64, 128), (1000, 48, 77), (65, 16, 5)])
+def test_vq_assign_small(xgs, n, d, k):
+    X, E = vq_case(n, d, k, 16)
+    ri, d1, d2 = oracle.vq_assign(X, E)
+    Eb, en = xgs.xgs_vq_prepare(t(E))
+    for prec in (xgs.VQ_FP32, xgs.VQ_BF16_RESCORE4):
+        idx, dist = xgs.xgs_vq_assign(t(X), t(E), Eb, en, prec)
+        torch.cuda.synchronize()
+        idx = np_(idx)
+        raw, adj = agreement(idx, ri, d1, d2)
+        assert adj >= 0.999, (prec, raw, adj)
+        # the reported distance is the FP32 squared distance of the chosen codeword
+        chosen = ((X.astype(np.float64) - E[idx].astype(np.float64)) ** 2).sum(1)
+        assert rel_max(np_(dist), chosen) < 1e-5
+    if n == 12_288:
+        assert raw >= 0.999
+
+
+def test_vq_prepare_is_bf16_rounding(xgs):
+    E = synth.vq_codebook(64, 32, 8, seed=9, centre_seed=8)
+    Eb, en = xgs.xgs_vq_prepare(t(E))
+    torch.cuda.synchronize()
+    eb = np_(Eb).view(np.uint16)
+    ref = torch.from_numpy(E).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    np.testing.assert_array_equal(eb, ref)
+    f = torch.from_numpy(ref.view(np.int16)).view(torch.bfloat16).float().numpy().astype(np.float64)
+    assert rel_max(np_(en), (f * f).sum(1)) < 1e-6
+
+
+def test_vq_assign_precision_form_sampled(xgs):
+    """816,000 x 768 against K = 4,096 (the precision form): the full batch runs
+    on the GPU in both precisions; agreement with the FP64 oracle is measured on
+    a seeded 4,096-row sample (the oracle's brute force)."""
+    X, E = vq_case(816_000, 768, 4096, 256, seed=30)
+    Xg, Eg = t(X), t(E)
+    Eb, en = xgs.xgs_vq_prepare(Eg)
+    idx_b, _ = xgs.xgs_vq_assign(Xg, Eg, Eb, en, xgs.VQ_BF16_RESCORE4)
+    idx_f, _ = xgs.xgs_vq_assign(Xg, Eg, Eb, en, xgs.VQ_FP32)
+    torch.cuda.synchronize()
+    rows = np.sort(np.random.default_rng(31).choice(len(X), 4096, replace=False))
+    ri, d1, d2 = oracle.vq_assign(X[rows], E)
+    raw_b, adj_b = agreement(np_(idx_b)[rows], ri, d1, d2)
+    raw_f, adj_f = agreement(np_(idx_f)[rows], ri, d1, d2)
+    print(f"agreement bf16+rescore raw {raw_b:.5f} tie-adjusted {adj_b:.5f}; fp32 raw {raw_f:.5f} adj {adj_f:.5f}")
+    assert adj_b >= 0.999 and adj_f >= 0.999
+
+
+def test_vq_edge_cases(xgs):
+    # duplicated codewords: ties go to the lowest index on both paths
+    E = np.array([[1, 0, 0, 0] * 4, [0, 1, 0, 0] * 4, [1, 0, 0, 0] * 4, [0, 1, 0, 0] * 4], np.float32)
+    X = np.array([[1, 0, 0, 0] * 4, [0, 1, 0, 0] * 4, [0.5, 0.5, 0, 0] * 4], np.float32)
+    Eb, en = xgs.xgs_vq_prepare(t(E))
+    for prec in (xgs.VQ_FP32, xgs.VQ_BF16_RESCORE4):
+        idx, _ = xgs.xgs_vq_assign(t(X), t(E), Eb, en, prec)
+        torch.cuda.synchronize()
+        assert list(np_(idx)) == [0, 1, 0], prec
+    with pytest.raises(xgs.XgsError):
+        xgs.xgs_vq_assign(t(X[:, :15].copy()), t(E[:, :15].copy()), Eb, en, xgs.VQ_BF16_RESCORE4)
+    idx, dist = xgs.xgs_vq_assign(t(X[:0].copy()), t(E), Eb, en, xgs.VQ_BF16_RESCORE4)
+    assert idx.numel() == 0
+
+
+# ------------------------------------------------------------------ a7
+@pytest.mark.parametrize("mode", ["paper", "laplace"])
+def test_ema_update_matches_oracle(xgs, mode):
+    X, E = vq_case(12_288, 64, 128, 16)
+    m = xgs.EMA_PAPER if mode == "paper" else xgs.EMA_LAPLACE
+    ri, _, _ = oracle.vq_assign(X, E)
+    N0, M0 = oracle.ema_init(E)
+    Nr, Mr, Er, cr, _ = oracle.ema_update(X, ri, N0, M0, 0.99, 1e-5, m)
+    Ng, Mg, Eg = t(N0.astype(np.float32)), t(M0.astype(np.float32)), t(E)
+    Eb, en = xgs.xgs_vq_prepare(Eg)
+    counts = xgs.xgs_vq_ema_update(t(X), t(ri.astype(np.int32)), Ng, Mg, Eg, Eb, en, 0.99, 1e-5, m)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(np_(counts), cr)
+    assert rel_max(np_(Ng), Nr) < 1e-6
+    assert rel_max(np_(Mg), Mr) < 1e-5
+    assert rel_max(np_(Eg), Er) < 1e-5
+    # the shadow follows the new codebook
+    ref = torch.from_numpy(np_(Eg)).to(torch.bfloat16).view(torch.int16).numpy()
+    np.testing.assert_array_equal(np_(Eb), ref)
+
+
+def test_ema_update_is_bitwise_reproducible(xgs):
+    X, E = vq_case(50_000, 64, 128, 16, seed=7)
+    idx = t(np.random.default_rng(1).integers(0, 128, len(X)).astype(np.int32))
+    outs = []
+    for _ in range(2):
+        N0, M0 = oracle.ema_init(E)
+        Ng, Mg, Eg = t(N0.astype(np.float32)), t(M0.astype(np.float32)), t(E)
+        xgs.xgs_vq_ema_update(t(X), idx, Ng, Mg, Eg, None, None, 0.99, 1e-5, xgs.EMA_LAPLACE)
+        torch.cuda.synchronize()
+        outs.append((np_(Ng), np_(Mg), np_(Eg)))
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_ema_update_no_samples(xgs):
+    E = synth.vq_codebook(16, 8, 4, seed=2, centre_seed=1)
+    N0, M0 = oracle.ema_init(E)
+    Ng, Mg, Eg = t(N0.astype(np.float32)), t(M0.astype(np.float32)), t(E)
+    X0 = torch.empty((0, 8), device="cuda")
+    i0 = torch.empty(0, dtype=torch.int32, device="cuda")
+    xgs.xgs_vq_ema_update(X0, i0, Ng, Mg, Eg, None, None, 0.99, 1e-5, xgs.EMA_PAPER)
+    torch.cuda.synchronize()
+    assert rel_max(np_(Ng), 0.99 * N0) < 1e-6

@@ -39,7 +39,7 @@ def with_field(s, name, arr):
 
 
 def trace(r):
-    return (r.n_last.copy(), r.proj.rect.copy())
+    return (r.n_last.copy(), r.amb[3].copy(), r.proj.rect.copy())
 
 
 @pytest.mark.parametrize("seed", [0, 1])
