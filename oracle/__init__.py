@@ -53,7 +53,7 @@ def lib():
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
         _lib = ctypes.CDLL(_LIB)
-        for name in ("orc_project", "orc_composite_fwd", "orc_composite_list", "orc_composite_bwd",
+        for name in ("orc_project", "orc_composite_fwd", "orc_composite_list", "orc_composite_bwd", "orc_composite_tiles",
                      "orc_project_bwd", "orc_vq_assign", "orc_grid_info"):
             getattr(_lib, name).restype = ctypes.c_int
         _lib.orc_bin.restype = ctypes.c_int64
@@ -176,6 +176,53 @@ def render(scene, cam, tile_mask=None) -> Render:
     chan = channels(scene, pr.depth)
     out, fT, nl, amb = composite_fwd(pr, scene.opacity, chan, order, ranges, cam, tile_mask)
     return Render(pr, keys, order, ranges, out, fT, nl, amb, chan)
+
+
+def render_tiles(scene, cam, tiles):
+    """Project -> bin -> composite of the listed tiles only, returned compactly:
+    out [k][C][16][16], final_T [k][16][16], amb [k][4][16][16] (skip, stop and
+    depth-gap measures and the blend signature, as in Render.amb)."""
+    hs, ws, ty, tx = grid_info(cam)
+    pr = project(scene, cam)
+    keys, order, ranges = bin_instances(pr.rect, depth_bits(pr.depth), tx, ty)
+    chan = channels(scene, pr.depth)
+    tiles = np.ascontiguousarray(tiles, dtype=np.int32)
+    C = chan.shape[1]
+    out = np.zeros((len(tiles), C, 16, 16))
+    fT = np.ones((len(tiles), 16, 16))
+    amb = np.full((len(tiles), 4, 16, 16), np.inf)
+    amb[:, 3] = 0.0
+    lib().orc_composite_tiles(_p(_f64(pr.mean2d)), _p(_f64(pr.conic)), _p(_f64(scene.opacity)), _p(chan),
+                              _p(_f64(pr.depth)), ctypes.c_int32(C), _p(np.ascontiguousarray(order, np.uint32)),
+                              _p(np.ascontiguousarray(ranges, np.uint32)), _p(cam_array(cam)), _p(tiles),
+                              ctypes.c_int32(len(tiles)), _p(out), _p(fT), _p(amb))
+    return pr, out, fT, amb
+
+
+def tile_view(img, cam, tiles):
+    """[..., Hs, Ws] image -> [k, ..., 16, 16] stack of the listed tiles (zero past the edge)."""
+    hs, ws, ty, tx = grid_info(cam)
+    img = np.asarray(img)
+    lead = img.shape[:-2]
+    res = np.zeros((len(tiles),) + lead + (16, 16), dtype=img.dtype)
+    for q, t in enumerate(tiles):
+        y, x = divmod(int(t), tx)
+        blk = img[..., 16 * y:16 * y + 16, 16 * x:16 * x + 16]
+        res[(q,) + (slice(None),) * len(lead) + (slice(0, blk.shape[-2]), slice(0, blk.shape[-1]))] = blk
+    return res
+
+
+def untile(stack, cam, tiles):
+    """Inverse of tile_view: [k, ..., 16, 16] -> [..., Hs, Ws], zero elsewhere."""
+    hs, ws, ty, tx = grid_info(cam)
+    stack = np.asarray(stack)
+    lead = stack.shape[1:-2]
+    img = np.zeros(lead + (hs, ws), dtype=stack.dtype)
+    for q, t in enumerate(tiles):
+        y, x = divmod(int(t), tx)
+        h = min(16, hs - 16 * y); w = min(16, ws - 16 * x)
+        img[..., 16 * y:16 * y + h, 16 * x:16 * x + w] = stack[q, ..., :h, :w]
+    return img
 
 
 def composite_list(proj: Projection, opacity, chan, order, cam):

@@ -335,6 +335,39 @@ int orc_composite_fwd(int64_t n, const double* mean2d, const double* conic, cons
 }
 
 /*
+ * Same walk as orc_composite_fwd for a list of tiles only, written compactly:
+ * out[k][C][16][16], final_T[k][16][16], amb[k][4][16][16] (the measures of
+ * walk_pixel) for tile k = tiles[k]; pixels past the grid edge are left 0.
+ */
+int orc_composite_tiles(const double* mean2d, const double* conic, const double* opac,
+                        const double* chan, const double* depth, int32_t C, const uint32_t* order,
+                        const uint32_t* ranges, const double* cam, const int32_t* tiles, int32_t nt,
+                        double* out, double* final_T, double* amb) {
+    cam_t k; read_cam(cam, &k);
+    double* acc = (double*)malloc(sizeof(double) * C);
+    for (int q = 0; q < nt; ++q) {
+        int t = tiles[q];
+        int ty = t / k.tx, tx = t % k.tx;
+        uint32_t b = ranges[2 * t], e = ranges[2 * t + 1];
+        for (int r = 0; r < ORC_TILE; ++r)
+            for (int c = 0; c < ORC_TILE; ++c) {
+                int m = ty * ORC_TILE + r, nn = tx * ORC_TILE + c;
+                if (m >= k.Hs || nn >= k.Ws) continue;
+                double px = k.ox + (double)nn * k.s + 0.5, py = k.oy + (double)m * k.s + 0.5;
+                double a4[4]; int64_t nl;
+                double T = walk_pixel(px, py, order + b, (int64_t)e - b, mean2d, conic, opac, chan,
+                                      depth, C, acc, &nl, a4);
+                int64_t p = (int64_t)r * ORC_TILE + c;
+                for (int ch = 0; ch < C; ++ch) out[((int64_t)q * C + ch) * 256 + p] = acc[ch];
+                final_T[(int64_t)q * 256 + p] = T;
+                for (int j = 0; j < 4; ++j) amb[((int64_t)q * 4 + j) * 256 + p] = a4[j];
+            }
+    }
+    free(acc);
+    return 0;
+}
+
+/*
  * Brute-force composite: every pixel walks the same global list (all visible
  * Gaussians in (depth, index) order), no tiles.  Same outputs as above.
  */

@@ -23,8 +23,12 @@ xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint
 // Stable LSD radix sort of the first *count pairs (count <= cap) on key bits
 // [0, key_bits).  Pairs start in (k0, v0); the sorted result is left in
 // (k0, v0) if the number of 8-bit passes is even, otherwise in (k1, v1);
-// *in_first reports which.  hist must hold 256 * sort_blocks(cap) u32.
+// hist must hold radix_hist_words(cap, key_bits) u32.
 int radix_passes(int key_bits);
+inline int64_t radix_hist_words(int64_t cap, int key_bits) {
+    int64_t nb = sort_blocks(cap) > 0 ? sort_blocks(cap) : 1;
+    return 256 * nb + 256 * (int64_t)((key_bits + 7) / 8);
+}
 xgs_status radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
                       const int64_t* count, int64_t cap, int key_bits, uint32_t* hist,
                       hipStream_t stream);

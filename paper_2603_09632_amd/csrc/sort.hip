@@ -125,10 +125,13 @@ xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint
 }
 
 // ------------------------------------------------------------ radix sort
+// Per block: digit histogram of its 4096 keys, written digit-major
+// (hist[d * nb + b]); per digit: a running total over all blocks.
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t* __restrict__ keys,
                                                                  const int64_t* __restrict__ count,
                                                                  int shift, uint32_t mask,
-                                                                 uint32_t* __restrict__ hist) {
+                                                                 uint32_t* __restrict__ hist,
+                                                                 uint32_t* __restrict__ totals) {
     __shared__ uint32_t h[256];
     const int64_t m = *count;
     const int64_t base = (int64_t)blockIdx.x * kSortItems;
@@ -142,30 +145,44 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t
         }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+    const uint32_t c = h[threadIdx.x];
+    hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = c;
+    if (c) atomicAdd(&totals[threadIdx.x], c);
 }
 
-// One block of 1024 threads: exclusive scan of the digit-major histogram.
-__global__ void __launch_bounds__(1024) radix_scan_kernel(uint32_t* hist, int64_t len) {
-    __shared__ uint32_t sh[1024];
-    const int t = threadIdx.x;
-    int64_t per = (len + 1023) / 1024;
-    int64_t b = t * per, e = b + per < len ? b + per : len;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += hist[i];
-    sh[t] = s;
+// One workgroup per digit d: offset of d = sum of the totals of smaller
+// digits, then an exclusive scan of d's per-block counts (contiguous, read in
+// coalesced chunks of 256).
+__global__ void __launch_bounds__(256) radix_scan_kernel(uint32_t* __restrict__ hist,
+                                                        const uint32_t* __restrict__ totals, int64_t nb) {
+    __shared__ uint32_t sh[256];
+    __shared__ uint32_t carry;
+    const int d = blockIdx.x, t = threadIdx.x;
+    sh[t] = t < d ? totals[t] : 0u;
     __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        uint32_t o = t >= d ? sh[t - d] : 0;
-        __syncthreads();
-        sh[t] += o;
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (t < o) sh[t] += sh[t + o];
         __syncthreads();
     }
-    uint32_t run = sh[t] - s;
-    for (int64_t i = b; i < e; ++i) {
-        uint32_t v = hist[i];
-        hist[i] = run;
-        run += v;
+    if (t == 0) carry = sh[0];
+    __syncthreads();
+    uint32_t* row = hist + (int64_t)d * nb;
+    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+        const int64_t i = b0 + t;
+        const uint32_t v = i < nb ? row[i] : 0u;
+        sh[t] = v;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const uint32_t x = t >= o ? sh[t - o] : 0u;
+            __syncthreads();
+            sh[t] += x;
+            __syncthreads();
+        }
+        const uint32_t c = carry;
+        if (i < nb) row[i] = c + sh[t] - v;
+        __syncthreads();
+        if (t == 255) carry = c + sh[255];
+        __syncthreads();
     }
 }
 
@@ -229,14 +246,17 @@ xgs_status radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, co
     int64_t nb = sort_blocks(cap);
     if (nb == 0) return XGS_OK;
     int passes = radix_passes(key_bits);
+    uint32_t* totals = hist + 256 * nb;  // 256 per pass
+    xgs_status s = fill_u32(totals, 256 * (int64_t)passes, 0u, stream);
+    if (s) return s;
     uint64_t* ki = k0; uint32_t* vi = v0; uint64_t* ko = k1; uint32_t* vo = v1;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
         int nbits = key_bits - shift < 8 ? key_bits - shift : 8;
         uint32_t mask = (1u << nbits) - 1u;
         hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, ki,
-                           count, shift, mask, hist);
-        hipLaunchKernelGGL(radix_scan_kernel, dim3(1), dim3(1024), 0, stream, hist, nb * 256);
+                           count, shift, mask, hist, totals + 256 * p);
+        hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(256), 0, stream, hist, totals + 256 * p, nb);
         hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream,
                            ki, vi, ko, vo, count, shift, mask, nbits, hist);
         uint64_t* tk = ki; ki = ko; ko = tk;

@@ -45,7 +45,7 @@ static SortWs carve_sort(void* base, int64_t n, int64_t cap, size_t* bytes) {
     w.partials = c.take<uint64_t>(scan_blocks(n) + 1);
     w.keys_alt = c.take<uint64_t>(cap > 0 ? cap : 1);
     w.vals_alt = c.take<uint32_t>(cap > 0 ? cap : 1);
-    w.hist = c.take<uint32_t>(256 * (sort_blocks(cap) > 0 ? sort_blocks(cap) : 1));
+    w.hist = c.take<uint32_t>(radix_hist_words(cap, 64));
     w.total = c.take<int64_t>(1);
     *bytes = c.total();
     return w;

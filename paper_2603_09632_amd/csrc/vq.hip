@@ -19,6 +19,7 @@ namespace xgs {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
     uint32_t u = __float_as_uint(f);
@@ -152,12 +153,17 @@ __device__ __forceinline__ void top4_insert(Top4& t, float s, int i) {
     }
 }
 
-__global__ void __launch_bounds__(256) vq_bf16_kernel(const float* __restrict__ X, int64_t N, int D,
+// NKC > 0: D = 16 * NKC is a compile-time constant and the K loop is fully
+// unrolled (no loop back-edge, so the prefetches stay in flight);
+// NKC == 0: runtime D, rolled loop.
+template <int PF, int NKC>
+__global__ void __launch_bounds__(256) vq_bf16_kernel(const float* __restrict__ X, int64_t N, int D_rt,
                                                      const float* __restrict__ E,
                                                      const uint16_t* __restrict__ Eb,
                                                      const float* __restrict__ en, int K,
                                                      int32_t* __restrict__ idx, float* __restrict__ dist) {
     extern __shared__ __align__(16) uint16_t xs[];  // [B_BM][D + B_PAD]
+    const int D = NKC > 0 ? 16 * NKC : D_rt;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int ld = D + B_PAD;
     const int64_t r0 = (int64_t)blockIdx.x * B_BM;
@@ -166,7 +172,11 @@ __global__ void __launch_bounds__(256) vq_bf16_kernel(const float* __restrict__ 
     for (int e = t; e < B_BM * q4; e += 256) {
         const int row = e / q4, c4 = e - row * q4;
         const int64_t gr = r0 + row;
-        float4 v = gr < N ? reinterpret_cast<const float4*>(X + gr * D)[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gr < N) {
+            const f32x4_t q = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t*>(X + gr * D) + c4);
+            v = make_float4(q[0], q[1], q[2], q[3]);
+        }
         uint2 p;
         p.x = (uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16);
         p.y = (uint32_t)to_bf16(v.z) | ((uint32_t)to_bf16(v.w) << 16);
@@ -185,6 +195,7 @@ __global__ void __launch_bounds__(256) vq_bf16_kernel(const float* __restrict__ 
     const uint16_t* xrow1 = xs + (32 + col) * ld + 8 * half;
     const int per_wave = (K + 3) / 4;  // codewords swept by this wave: [w*per_wave, ...)
     const int cw0 = w * per_wave, cw1 = min(K, cw0 + per_wave);
+    const int nk = D / 16;
     for (int c0 = cw0; c0 < cw1; c0 += 32 * B_FRAGS) {
         f32x16_t acc[B_FRAGS][2];
         const uint16_t* arow[B_FRAGS];
@@ -196,23 +207,47 @@ __global__ void __launch_bounds__(256) vq_bf16_kernel(const float* __restrict__ 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int c = cbase + 8 * g4 + 4 * half + r;
-                    const float init = c < cw1 ? -0.5f * en[c] : -INFINITY;
+                    const float v = en[min(c, K - 1)];
+                    const float init = c < cw1 ? -0.5f * v : -INFINITY;
                     acc[f][0][4 * g4 + r] = init;
                     acc[f][1][4 * g4 + r] = init;
                 }
             }
-            int ca = cbase + col;
-            ca = ca < K ? ca : K - 1;
-            arow[f] = Eb + (size_t)ca * D + 8 * half;
+            arow[f] = Eb + (size_t)min(cbase + col, K - 1) * D + 8 * half;
         }
-        for (int k0 = 0; k0 < D; k0 += 16) {
-            const bf16x8_t b0 = *reinterpret_cast<const bf16x8_t*>(xrow0 + k0);
-            const bf16x8_t b1 = *reinterpret_cast<const bf16x8_t*>(xrow1 + k0);
+        // A fragments are loaded PF k-steps ahead of their use, the X
+        // fragments from LDS one step ahead.
+        bf16x8_t abuf[PF][B_FRAGS];
 #pragma unroll
-            for (int f = 0; f < B_FRAGS; ++f) {
-                const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(arow[f] + k0);
-                acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc[f][0], 0, 0, 0);
-                acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc[f][1], 0, 0, 0);
+        for (int s = 0; s < PF; ++s)
+#pragma unroll
+            for (int f = 0; f < B_FRAGS; ++f)
+                abuf[s][f] = *reinterpret_cast<const bf16x8_t*>(arow[f] + 16 * min(s, nk - 1));
+        bf16x8_t b0 = *reinterpret_cast<const bf16x8_t*>(xrow0);
+        bf16x8_t b1 = *reinterpret_cast<const bf16x8_t*>(xrow1);
+        // nk is a multiple of PF (the host picks PF accordingly)
+#pragma unroll
+        for (int k = 0; k < (NKC > 0 ? NKC : nk); k += PF) {
+#pragma unroll
+            for (int s = 0; s < PF; ++s) {
+                const int kk = k + s;
+                const int kb = min(kk + 1, nk - 1);
+                const bf16x8_t nb0 = *reinterpret_cast<const bf16x8_t*>(xrow0 + 16 * kb);
+                const bf16x8_t nb1 = *reinterpret_cast<const bf16x8_t*>(xrow1 + 16 * kb);
+#pragma unroll
+                for (int f = 0; f < B_FRAGS; ++f) {
+                    acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abuf[s][f], b0, acc[f][0], 0, 0, 0);
+                    acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abuf[s][f], b1, acc[f][1], 0, 0, 0);
+                }
+                const int kn = min(kk + PF, nk - 1);
+#pragma unroll
+                for (int f = 0; f < B_FRAGS; ++f)
+                    abuf[s][f] = *reinterpret_cast<const bf16x8_t*>(arow[f] + 16 * kn);
+                b0 = nb0;
+                b1 = nb1;
+                // keep the prefetches where they are: the scheduler would
+                // otherwise sink them next to their use, PF steps later
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         // top-4 per row: candidates i = c0 + 32 f + 8 (r/4) + 4 half + r%4
@@ -312,23 +347,59 @@ __global__ void ema_keys_kernel(const int32_t* __restrict__ idx, int64_t N, int 
     vals[n] = (uint32_t)n;
 }
 
-// One workgroup per codeword: counts, in-order row sums, EMA of N and M.
+// One workgroup per codeword: counts, row sums in ascending row order, EMA of
+// N and M.  Row ids are staged in LDS; each thread owns up to 4 columns and
+// issues the loads of 8 rows before adding them in order, so the sum order
+// (and hence the result) does not depend on timing.
+constexpr int EMA_COLS = 4, EMA_ROWS = 8;
+
 __global__ void __launch_bounds__(256) ema_accum_kernel(const float* __restrict__ X, int D,
                                                        const uint32_t* __restrict__ rows,
                                                        const uint32_t* __restrict__ ranges,
                                                        float decay, float* __restrict__ N_ema,
                                                        float* __restrict__ M_ema,
                                                        float* __restrict__ counts) {
-    const int l = blockIdx.x;
+    __shared__ uint32_t rid[256];
+    const int l = blockIdx.x, t = threadIdx.x;
     const uint32_t b = ranges[2 * l], e = ranges[2 * l + 1];
-    const float c = (float)(e - b);
-    for (int d = threadIdx.x; d < D; d += 256) {
-        float s = 0.f;
-        for (uint32_t k = b; k < e; ++k) s += X[(size_t)rows[k] * D + d];
-        float* m = M_ema + (size_t)l * D + d;
-        *m = decay * *m + (1.f - decay) * s;
+    for (int d0 = 0; d0 < D; d0 += 256 * EMA_COLS) {
+        float acc[EMA_COLS];
+#pragma unroll
+        for (int c = 0; c < EMA_COLS; ++c) acc[c] = 0.f;
+        for (uint32_t k0 = b; k0 < e; k0 += 256) {
+            __syncthreads();
+            if (k0 + t < e) rid[t] = rows[k0 + t];
+            __syncthreads();
+            const int cnt = (int)min(256u, e - k0);
+            for (int k = 0; k < cnt; k += EMA_ROWS) {
+                float v[EMA_ROWS][EMA_COLS];
+#pragma unroll
+                for (int j = 0; j < EMA_ROWS; ++j) {
+                    const bool rok = k + j < cnt;
+                    const size_t base = rok ? (size_t)rid[k + j] * D : 0;
+#pragma unroll
+                    for (int c = 0; c < EMA_COLS; ++c) {
+                        const int d = d0 + t + 256 * c;
+                        v[j][c] = (rok && d < D) ? X[base + d] : 0.f;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < EMA_ROWS; ++j)
+#pragma unroll
+                    for (int c = 0; c < EMA_COLS; ++c) acc[c] += v[j][c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < EMA_COLS; ++c) {
+            const int d = d0 + t + 256 * c;
+            if (d < D) {
+                float* m = M_ema + (size_t)l * D + d;
+                *m = decay * *m + (1.f - decay) * acc[c];
+            }
+        }
     }
-    if (threadIdx.x == 0) {
+    if (t == 0) {
+        const float c = (float)(e - b);
         N_ema[l] = decay * N_ema[l] + (1.f - decay) * c;
         if (counts) counts[l] = c;
     }
@@ -401,7 +472,7 @@ static EmaWs carve_ema(void* base, int64_t N, int K, size_t* bytes) {
     w.vals = c.take<uint32_t>(n1);
     w.keys_alt = c.take<uint64_t>(n1);
     w.vals_alt = c.take<uint32_t>(n1);
-    w.hist = c.take<uint32_t>(256 * (sort_blocks(n1) > 0 ? sort_blocks(n1) : 1));
+    w.hist = c.take<uint32_t>(radix_hist_words(n1, 64));
     w.ranges = c.take<uint32_t>(2 * (size_t)(K > 0 ? K : 1));
     w.count = c.take<int64_t>(1);
     w.total = c.take<float>(1);
@@ -460,11 +531,32 @@ extern "C" xgs_status xgs_vq_assign(const float* X, int64_t N, int32_t D, const 
     const size_t lds_bytes = lds > lds_cand ? lds : lds_cand;
     if (lds_bytes > 160 * 1024) return fail(XGS_ERR_UNSUPPORTED, "xgs_vq_assign: D too large for the LDS-resident row tile");
     const int64_t blocks = (N + B_BM - 1) / B_BM;
-    if (hipFuncSetAttribute((const void*)vq_bf16_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds_bytes) != hipSuccess)
+    const int nk = D / 16;
+    const void* fn;
+    void (*launch)(dim3, size_t, hipStream_t, const float*, int64_t, int, const float*, const uint16_t*,
+                   const float*, int, int32_t*, float*);
+#define XGS_VQ_KERNEL(PF, NKC)                                                                          \
+    fn = (const void*)vq_bf16_kernel<PF, NKC>;                                                          \
+    launch = [](dim3 g, size_t l, hipStream_t s, const float* X_, int64_t N_, int D_, const float* E_,  \
+                const uint16_t* Eb_, const float* en_, int K_, int32_t* i_, float* d_) {                \
+        hipLaunchKernelGGL((vq_bf16_kernel<PF, NKC>), g, dim3(256), l, s, X_, N_, D_, E_, Eb_, en_, K_, \
+                           i_, d_);                                                                      \
+    };
+    switch (nk) {
+        case 48: XGS_VQ_KERNEL(4, 48) break;
+        case 32: XGS_VQ_KERNEL(4, 32) break;
+        case 16: XGS_VQ_KERNEL(4, 16) break;
+        case 8: XGS_VQ_KERNEL(4, 8) break;
+        case 4: XGS_VQ_KERNEL(4, 4) break;
+        default:
+            if (nk % 4 == 0) { XGS_VQ_KERNEL(4, 0) }
+            else if (nk % 2 == 0) { XGS_VQ_KERNEL(2, 0) }
+            else { XGS_VQ_KERNEL(1, 0) }
+    }
+#undef XGS_VQ_KERNEL
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess)
         return fail(XGS_ERR_HIP, "xgs_vq_assign: cannot reserve " + std::to_string(lds_bytes) + " bytes of LDS");
-    hipLaunchKernelGGL(vq_bf16_kernel, dim3((unsigned)blocks), dim3(256), lds_bytes, st, X, N, D, E, E_bf16,
-                       e_norm2, K, idx, dist);
+    launch(dim3((unsigned)blocks), lds_bytes, st, X, N, D, E, E_bf16, e_norm2, K, idx, dist);
     return check_launch("xgs_vq_assign bf16");
 }
 

@@ -299,3 +299,19 @@ def test_sampled_grid_picks_dense_pixels(orc):
         sp = orc.render(s, synth.tiny_camera().with_grid(stride, oy, ox)).out
         ref = dense[:, oy::stride, ox::stride]
         np.testing.assert_allclose(sp[:, :ref.shape[1], :ref.shape[2]], ref, rtol=0, atol=1e-12)
+
+
+def test_tile_list_composite_equals_full_frame(orc):
+    """The compact per-tile walk writes the same values as the full frame."""
+    s = synth.tiny_scene(seed=16, n=900)
+    cam = synth.tiny_camera().with_grid(2, 1, 0)
+    hs, ws, ty, tx = orc.grid_info(cam)
+    r = orc.render(s, cam)
+    tiles = [0, 3, tx * ty - 1, tx]
+    pr, out, fT, amb = orc.render_tiles(s, cam, tiles)
+    np.testing.assert_array_equal(out, orc.tile_view(r.out, cam, tiles))
+    np.testing.assert_array_equal(amb[:, 3], orc.tile_view(r.amb[3], cam, tiles))
+    np.testing.assert_array_equal(orc.untile(out, cam, tiles), r.out * orc.untile(np.ones((len(tiles), 16, 16)), cam, tiles)[None])
+    ft = orc.tile_view(r.final_T, cam, tiles)
+    inside = orc.tile_view(np.ones((hs, ws)), cam, tiles) == 1
+    np.testing.assert_array_equal(fT[inside], ft[inside])
