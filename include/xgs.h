@@ -154,6 +154,12 @@ xgs_status xgs_grid_dims(const xgs_camera* cam, int32_t* hs, int32_t* ws,
  * that misses the sampled grid.  One thread per Gaussian; n may be 0. */
 xgs_status xgs_project(const xgs_gaussians* g, const xgs_camera* cam, xgs_projected* out,
                        xgs_stream_t stream);
+/* Same, with the world->camera matrix read from device memory (d_viewmat,
+ * row-major 4x4 floats) instead of cam->viewmat: a captured HIP graph can then
+ * be replayed for a new pose by rewriting those 16 floats.  Intrinsics, image
+ * size and grid still come from *cam. */
+xgs_status xgs_project_posed(const xgs_gaussians* g, const xgs_camera* cam, const float* d_viewmat,
+                             xgs_projected* out, xgs_stream_t stream);
 
 /* ------------------------------------------------------- a2: tile sort
  * Binning and depth sort ("depth-sorted Gaussians", Sec. 3.1): exclusive scan

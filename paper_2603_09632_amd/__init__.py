@@ -32,7 +32,7 @@ BWD_ALL, BWD_FEATURES_ONLY = 0, 1
 
 __all__ = [
     "XgsError", "Gaussians", "Projected", "Binning", "camera", "camera_from", "grid_dims",
-    "xgs_project", "alloc_binning", "xgs_tile_sort", "xgs_render_fwd", "xgs_render_bwd",
+    "xgs_project", "xgs_project_posed", "alloc_binning", "xgs_tile_sort", "xgs_render_fwd", "xgs_render_bwd",
     "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_ema_update", "render",
 ]
 
@@ -162,6 +162,17 @@ def xgs_project(g: Gaussians, cam, out: Optional[Projected] = None, stream=None)
     out = out or Projected.alloc(g.n, g.means.device)
     gs, ps = g.struct(), out.struct()
     check(lib.xgs_project(ctypes.byref(gs), ctypes.byref(c), ctypes.byref(ps), _stream(stream)), "xgs_project")
+    return out
+
+
+def xgs_project_posed(g: Gaussians, cam, viewmat_dev: torch.Tensor, out: Optional[Projected] = None,
+                      stream=None) -> Projected:
+    """Projection with the world->camera matrix taken from a device tensor [4,4]."""
+    c = camera_from(cam)
+    out = out or Projected.alloc(g.n, g.means.device)
+    gs, ps = g.struct(), out.struct()
+    check(lib.xgs_project_posed(ctypes.byref(gs), ctypes.byref(c), _ptr(viewmat_dev), ctypes.byref(ps),
+                                _stream(stream)), "xgs_project_posed")
     return out
 
 

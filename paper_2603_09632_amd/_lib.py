@@ -51,6 +51,7 @@ SIGNATURES = {
     "xgs_version": (c_int32, []),
     "xgs_grid_dims": (c_int32, [P(XgsCamera), P(c_int32), P(c_int32), P(c_int32), P(c_int32)]),
     "xgs_project": (c_int32, [P(XgsGaussians), P(XgsCamera), P(XgsProjected), c_void_p]),
+    "xgs_project_posed": (c_int32, [P(XgsGaussians), P(XgsCamera), c_void_p, P(XgsProjected), c_void_p]),
     "xgs_tile_sort_workspace": (c_size_t, [c_int64, c_int64, c_int32]),
     "xgs_tile_sort": (c_int32, [P(XgsProjected), P(XgsCamera), c_int64, c_void_p, c_size_t,
                                 P(XgsBinning), c_void_p]),
@@ -81,7 +82,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise ImportError(f"{path} is missing: build it with `python -m paper_2603_09632_amd.build`")
+        raise ImportError(f"{path} is missing: build it with `python paper_2603_09632_amd/build.py`")
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -1,6 +1,7 @@
 """Builds libxgs.so (all HIP sources, gfx950 only) in-tree with hipcc.
 
-Usage: python -m paper_2603_09632_amd.build   (or build() from Python)
+Usage: python paper_2603_09632_amd/build.py   (run as a script: importing the
+package would load the library being rebuilt)
 """
 from __future__ import annotations
 

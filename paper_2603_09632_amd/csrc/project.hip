@@ -12,13 +12,23 @@ struct CamDev {
     int s, oy, ox, hs, ws;
 };
 
+// viewmat (optional): world->camera matrix in device memory, row-major 4x4;
+// when given it replaces the rotation and translation in c.
 __global__ void __launch_bounds__(256) project_kernel(
     int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float4* __restrict__ quats, const float* __restrict__ opacity, CamDev c,
-    float4* __restrict__ splat, int32_t* __restrict__ radius, uint2* __restrict__ tile_rect,
-    uint32_t* __restrict__ touched) {
+    const float* __restrict__ viewmat, float4* __restrict__ splat, int32_t* __restrict__ radius,
+    uint2* __restrict__ tile_rect, uint32_t* __restrict__ touched) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (viewmat) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) c.R[3 * r + k] = viewmat[4 * r + k];
+            c.t[r] = viewmat[4 * r + 3];
+        }
+    }
     const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
     const float o = opacity[i];
     float px = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
@@ -112,22 +122,22 @@ __global__ void __launch_bounds__(256) project_kernel(
 
 using namespace xgs;
 
-extern "C" xgs_status xgs_project(const xgs_gaussians* g, const xgs_camera* cam,
-                                  xgs_projected* out, xgs_stream_t stream) {
+static xgs_status project_impl(const xgs_gaussians* g, const xgs_camera* cam, const float* d_viewmat,
+                               xgs_projected* out, xgs_stream_t stream, const char* name) {
     clear_error();
-    if (!g || !cam || !out) return fail(XGS_ERR_INVALID_ARG, "xgs_project: null argument");
+    if (!g || !cam || !out) return fail(XGS_ERR_INVALID_ARG, std::string(name) + ": null argument");
     if (xgs_status s = validate_camera(cam)) return s;
-    if (g->n < 0) return fail(XGS_ERR_INVALID_ARG, "xgs_project: n < 0");
+    if (g->n < 0) return fail(XGS_ERR_INVALID_ARG, std::string(name) + ": n < 0");
     if (g->n == 0) return XGS_OK;
     if (!g->means || !g->log_scales || !g->quats || !g->opacity)
-        return fail(XGS_ERR_INVALID_ARG, "xgs_project: null Gaussian array");
+        return fail(XGS_ERR_INVALID_ARG, std::string(name) + ": null Gaussian array");
     if (!out->splat || !out->radius || !out->tile_rect || !out->tiles_touched)
-        return fail(XGS_ERR_INVALID_ARG, "xgs_project: null output array");
+        return fail(XGS_ERR_INVALID_ARG, std::string(name) + ": null output array");
     if (!aligned(g->quats, 16) || !aligned(out->splat, 16) || !aligned(out->tile_rect, 8))
-        return fail(XGS_ERR_INVALID_ARG, "xgs_project: quats/splat need 16-byte, tile_rect 8-byte alignment");
+        return fail(XGS_ERR_INVALID_ARG, std::string(name) + ": quats/splat need 16-byte, tile_rect 8-byte alignment");
     Grid gr = grid_of(*cam);
     if (gr.tx > 65535 || gr.ty > 65535)
-        return fail(XGS_ERR_UNSUPPORTED, "xgs_project: more than 65535 tiles along an axis");
+        return fail(XGS_ERR_UNSUPPORTED, std::string(name) + ": more than 65535 tiles along an axis");
     CamDev c;
     c.fx = cam->fx; c.fy = cam->fy; c.cx = cam->cx; c.cy = cam->cy; c.near_ = cam->near_plane;
     c.limx = kGuard * (0.5f * cam->width) / cam->fx;
@@ -140,7 +150,19 @@ extern "C" xgs_status xgs_project(const xgs_gaussians* g, const xgs_camera* cam,
     int64_t blocks = (g->n + 255) / 256;
     hipLaunchKernelGGL(project_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                        g->n, g->means, g->log_scales, reinterpret_cast<const float4*>(g->quats),
-                       g->opacity, c, reinterpret_cast<float4*>(out->splat), out->radius,
+                       g->opacity, c, d_viewmat, reinterpret_cast<float4*>(out->splat), out->radius,
                        reinterpret_cast<uint2*>(out->tile_rect), out->tiles_touched);
-    return check_launch("xgs_project");
+    return check_launch(name);
+}
+
+extern "C" xgs_status xgs_project(const xgs_gaussians* g, const xgs_camera* cam,
+                                  xgs_projected* out, xgs_stream_t stream) {
+    return project_impl(g, cam, nullptr, out, stream, "xgs_project");
+}
+
+extern "C" xgs_status xgs_project_posed(const xgs_gaussians* g, const xgs_camera* cam,
+                                        const float* d_viewmat, xgs_projected* out,
+                                        xgs_stream_t stream) {
+    if (!d_viewmat) return fail(XGS_ERR_INVALID_ARG, "xgs_project_posed: null device viewmat");
+    return project_impl(g, cam, d_viewmat, out, stream, "xgs_project_posed");
 }

@@ -20,7 +20,7 @@ def declared():
 @pytest.fixture(scope="module")
 def xgs():
     if not os.path.exists(LIB):
-        pytest.fail("libxgs.so is not built (python -m paper_2603_09632_amd.build)")
+        pytest.fail("libxgs.so is not built (python paper_2603_09632_amd/build.py)")
     import paper_2603_09632_amd as x
     return x
 

@@ -1,0 +1,108 @@
+"""Serving form: continuous batching over resident scenes.  Each request's
+image is bit-identical alone and in a mix; graph replays equal eager runs;
+admission respects the HBM budget; capacity overflow is recovered."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import np_, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def xgs():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def world(xgs):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    scenes = {}
+    for k, n in enumerate((40_000, 90_000, 150_000)):
+        s = synth.room_scene(n, seed=40 + k, c_sem=16)
+        scenes[f"room{k}"] = xgs.Gaussians(t(s.means), t(s.log_scales), t(s.quats), t(s.opacity), t(s.colors),
+                                           t(s.features))
+    from paper_2603_09632_amd.serve import Resolution
+    res = [Resolution(320, 240, 262.5, 262.5, 160, 120), Resolution(640, 480, 525, 525, 320, 240),
+           Resolution(1200, 680, 600, 600, 600, 340)]
+    poses = synth.room_trajectory(100, seed=10)
+    rng = np.random.default_rng(48)
+    reqs = [(f"room{rng.integers(0, 3)}", poses[rng.integers(0, 100)], res[rng.integers(0, 3)]) for _ in range(24)]
+    return scenes, res, reqs
+
+
+def direct(xgs, g, vm, r):
+    cam = xgs.camera(r.width, r.height, r.fx, r.fy, r.cx, r.cy, viewmat=vm)
+    out, fT, nl, p, b = xgs.render(g, cam)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_alone_equals_mixed_and_direct(xgs, world):
+    from paper_2603_09632_amd.serve import Server
+    scenes, res, reqs = world
+    alone = []
+    srv = Server(scenes, hbm_budget_bytes=8 << 30, max_inflight=1)
+    for sc, vm, r in reqs:
+        alone.append(np_(srv.render_now(sc, vm, r).image))
+    srv.close()
+    srv = Server(scenes, hbm_budget_bytes=8 << 30, max_inflight=8)
+    futs = [srv.submit(sc, vm, r) for sc, vm, r in reqs]
+    mixed = [np_(f.result(timeout=120).image) for f in futs]
+    st = srv.stats()
+    srv.close()
+    for a, m in zip(alone, mixed):
+        np.testing.assert_array_equal(a, m)
+    for (sc, vm, r), a in list(zip(reqs, alone))[:6]:
+        np.testing.assert_array_equal(a, np_(direct(xgs, scenes[sc], vm, r)))
+    assert st["completed"] == len(reqs)
+
+
+def test_graph_replays_match_eager(xgs, world):
+    from paper_2603_09632_amd.serve import Server
+    scenes, res, reqs = world
+    eager = Server(scenes, use_graphs=False, max_inflight=1)
+    graph = Server(scenes, use_graphs=True, max_inflight=1)
+    sc, _, r = reqs[0]
+    poses = synth.room_trajectory(100, seed=10)
+    for k in range(5):  # several replays of one captured graph, eager work in between
+        vm = poses[7 * k]
+        a = np_(eager.render_now(sc, vm, r).image)
+        b = np_(graph.render_now(sc, vm, r).image)
+        torch.randn(1000, device="cuda").sum().item()
+        np.testing.assert_array_equal(a, b)
+    eager.close()
+    graph.close()
+
+
+def test_admission_respects_budget(xgs, world):
+    from paper_2603_09632_amd.serve import Server
+    scenes, res, reqs = world
+    srv = Server(scenes, hbm_budget_bytes=1 << 30, max_inflight=8)
+    one = srv._estimate("room2", res[2])
+    srv.close()
+    budget = int(2.5 * one)
+    srv = Server(scenes, hbm_budget_bytes=budget, max_inflight=8)
+    futs = [srv.submit("room2", synth.room_trajectory(100, seed=10)[k], res[2]) for k in range(10)]
+    for f in futs:
+        f.result(timeout=120)
+    assert srv.peak_ledger_bytes <= budget
+    srv.close()
+    tiny = Server(scenes, hbm_budget_bytes=one // 4, max_inflight=8)
+    with pytest.raises(MemoryError):
+        tiny.submit("room2", synth.room_trajectory(100, seed=10)[0], res[2]).result(timeout=60)
+    tiny.close()
+
+
+def test_capacity_overflow_is_recovered(xgs, world):
+    from paper_2603_09632_amd.serve import Server
+    scenes, res, reqs = world
+    srv = Server(scenes, max_inflight=2)
+    sc, vm, r = "room1", synth.room_trajectory(100, seed=10)[3], res[1]
+    srv._capacity[(sc, r)] = 1000  # far too small: the graph's sort overflows
+    img = np_(srv.render_now(sc, vm, r).image)
+    assert srv.overflows == 1
+    srv.close()
+    np.testing.assert_array_equal(img, np_(direct(xgs, scenes[sc], vm, r)))
