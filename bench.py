@@ -126,12 +126,14 @@ def main():
     Mema = E0.clone()
     counts = torch.empty(4096, device=dev)
     ema_ws = torch.empty(int(xgs.lib.xgs_vq_ema_workspace(X.shape[0], 768, 4096)), dtype=torch.uint8, device=dev)
+    vq_ws = xgs.vq_assign_workspace(X.shape[0], 768, 4096, xgs.VQ_BF16_RESCORE4, dev)
     if args.calib_copy:
         src = torch.empty(256 * 1024 * 1024, device=dev)
         dst = torch.empty_like(src)
     torch.cuda.synchronize()
 
-    names = ["project", "tile_sort", "render_fwd", "render_bwd", "grid_sample", "vq_assign", "vq_ema"]
+    names = ["project", "tile_sort", "render_fwd", "render_bwd", "grid_sample", "vq_stage", "vq_gemm", "vq_rescore",
+             "vq_ema"]
     stream = torch.cuda.current_stream()
 
     def step(k, evs):
@@ -147,13 +149,19 @@ def main():
         evs[4].record(stream)
         xgs.xgs_grid_sample(P, 480, 640, G=G, V=V)
         evs[5].record(stream)
-        xgs.xgs_vq_assign(X, E, Eb, en, xgs.VQ_BF16_RESCORE4, idx=idx, dist=dist)
+        # xgs_vq_assign (BF16 + rescore) as its three stages, so that the
+        # MFMA sweep is timed on its own
+        xgs.xgs_vq_stage(X, Eb, en, vq_ws)
         evs[6].record(stream)
+        xgs.xgs_vq_candidates(X.shape[0], 768, 4096, vq_ws)
+        evs[7].record(stream)
+        xgs.xgs_vq_rescore(X, E, vq_ws, idx=idx, dist=dist)
+        evs[8].record(stream)
         xgs.xgs_vq_ema_update(X, idx, Nema, Mema, E, Eb, en, 0.99, 1e-5, xgs.EMA_LAPLACE, counts=counts,
                               workspace=ema_ws)
-        evs[7].record(stream)
+        evs[9].record(stream)
 
-    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
     log(f"warmup {args.warmup} steps")
     for k in range(args.warmup):
         step(k, mk())
@@ -178,7 +186,21 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
+    # the FP32 plain form of the same assignment, once (for the precision
+    # statement: the BF16 form must be faster at equal agreement)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    idx32 = torch.empty_like(idx)
+    dist32 = torch.empty_like(dist)
+    xgs.xgs_vq_assign(X, E, Eb, en, xgs.VQ_BF16_RESCORE4, idx=idx, dist=dist, workspace=vq_ws)
+    e0.record(stream)
+    xgs.xgs_vq_assign(X, E, Eb, en, xgs.VQ_FP32, idx=idx32, dist=dist32)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    vq_fp32_ms = e0.elapsed_time(e1)
+    vq_same = float((idx32 == idx).float().mean().item())
+
     ms = {n: float(np.mean(v)) for n, v in per.items()}
+    ms["vq_assign"] = ms["vq_stage"] + ms["vq_gemm"] + ms["vq_rescore"]
     frame = [sum(per[n][k] for n in names[:4]) for k in range(args.steps)]
     value = float(np.mean(frame))
     m_inst = int(b.num_instances.item())
@@ -186,19 +208,19 @@ def main():
     # ------------------------------------------------------------ rooflines
     N, D, K = X.shape[0], 768, 4096
     vq_flop = 2.0 * N * K * D
-    vq_tflops = vq_flop / (ms["vq_assign"] * 1e-3) / 1e12
-    vq_gbs = N * D * 4 / (ms["vq_assign"] * 1e-3) / 1e9
+    vq_tflops = vq_flop / (ms["vq_gemm"] * 1e-3) / 1e12
+    vq_assign_tflops = vq_flop / (ms["vq_assign"] * 1e-3) / 1e12
     grid_bytes = 512 * 480 * 640 * 4 + 480 * 640 + 512 * 30 * 40 * 4
     grid_gbs = grid_bytes / (ms["grid_sample"] * 1e-3) / 1e9
     # compositing forward: per instance val + splat + rgb + features; per pixel outputs
     fwd_bytes = m_inst * (4 + 32 + 12 + 4 * scene.c_sem) + hs * ws * 4 * (C + 2)
     fwd_gbs = fwd_bytes / (ms["render_fwd"] * 1e-3) / 1e9
-    timed = {"render_bwd": ms["render_bwd"], "vq_assign": ms["vq_assign"], "render_fwd": ms["render_fwd"]}
+    timed = {"render_bwd": ms["render_bwd"], "vq_gemm": ms["vq_gemm"], "render_fwd": ms["render_fwd"]}
     dominant = max(timed, key=timed.get)
-    if dominant == "vq_assign":
-        roof = {"kernel": "vq_bf16_kernel", "bound": "mfma", "achieved": round(vq_tflops, 2),
+    if dominant == "vq_gemm":
+        roof = {"kernel": "vq_gemm_kernel", "bound": "mfma", "achieved": round(vq_tflops, 2),
                 "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(vq_tflops / BF16_PEAK_TFLOPS, 4),
-                "traffic": traffic_for("vq_bf16_kernel", ["vq.hip"], vq_flop),
+                "traffic": traffic_for("vq_gemm_kernel", ["vq.hip"], vq_flop),
                 "algorithmic": f"2*N*K*D = {vq_flop:.3e} flop per launch (N=816000, K=4096, D=768)"}
     else:
         bwd_bytes = fwd_bytes + g.n * 4 * (3 + 3 + 4 + 1 + 3 + scene.c_sem) * 2
@@ -218,7 +240,8 @@ def main():
                    "instances_last_frame": m_inst},
         "ms": {k: round(v, 4) for k, v in ms.items()},
         "frame_ms_median": round(float(np.median(frame)), 4),
-        "vq_assign_GBps": round(vq_gbs, 1), "vq_assign_TFLOPs": round(vq_tflops, 1),
+        "vq_gemm_TFLOPs": round(vq_tflops, 1), "vq_assign_TFLOPs": round(vq_assign_tflops, 1),
+        "vq_fp32_plain_ms": round(vq_fp32_ms, 3), "vq_bf16_vs_fp32_same_index": round(vq_same, 6),
         "grid_sample_GBps": round(grid_gbs, 1), "render_fwd_alg_GBps": round(fwd_gbs, 1),
         "roofline": roof,
     }

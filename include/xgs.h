@@ -215,12 +215,17 @@ xgs_status xgs_grid_sample(const float* P, int32_t D, int32_t Hf, int32_t Wf, in
 /* ------------------------------------------------------ a6: VQ assignment
  * a_n = argmin_l ||x_n - E_l||^2 (Sec. 3.2.2), ties to the lowest l.
  * XGS_VQ_FP32: direct FP32 sum of (x - e)^2 over every codeword.
- * XGS_VQ_BF16_RESCORE4: ||e^||^2 - 2 x^.e^ with bf16 x^, e^ on MFMA (FP32
- * accumulation) keeps each row's 4 best codewords, which are then rescored
- * with the direct FP32 form.  E_bf16 [K][D] and e_norm2 [K] must hold
- * xgs_vq_prepare's output for E (xgs_vq_ema_update refreshes them).
- * BF16 requires D % 16 == 0.  idx [N] int32, dist [N] = FP32 squared
- * distance of the chosen codeword.  ws: xgs_vq_assign_workspace bytes. */
+ * XGS_VQ_BF16_RESCORE4: the squared distances of the bf16 roundings x^, e^
+ * are formed on MFMA (FP32 accumulation, the norms folded into the product)
+ * and each row keeps its 4 best codewords, ranked by half that distance with
+ * its lowest 6 + ceil(log2(min(16, ceil(K / 256)))) mantissa bits replaced
+ * by the codeword's position (ties to the lower index); the 4 are rescored
+ * with the direct FP32 form and the smallest wins.  E_bf16 [K][D] and
+ * e_norm2 [K] must hold xgs_vq_prepare's output for E (xgs_vq_ema_update
+ * refreshes them).  BF16 requires D % 8 == 0, K <= 65536, X and E_bf16
+ * 16-byte aligned, and ws (256-byte aligned) of xgs_vq_assign_workspace
+ * bytes (about N (D + 64) 2 bytes; zero for FP32).  idx [N] int32, dist [N] =
+ * FP32 squared distance of the chosen codeword. */
 size_t xgs_vq_assign_workspace(int64_t N, int32_t D, int32_t K, int32_t precision);
 xgs_status xgs_vq_prepare(const float* E, int32_t K, int32_t D, uint16_t* E_bf16, float* e_norm2,
                           xgs_stream_t stream);
@@ -228,6 +233,20 @@ xgs_status xgs_vq_assign(const float* X, int64_t N, int32_t D, const float* E,
                          const uint16_t* E_bf16, const float* e_norm2, int32_t K,
                          int32_t precision, int32_t* idx, float* dist, void* ws, size_t ws_bytes,
                          xgs_stream_t stream);
+
+/* The three stages of the XGS_VQ_BF16_RESCORE4 form, for callers that time
+ * or overlap them; xgs_vq_assign runs them in this order on one stream.  All
+ * share ws (xgs_vq_assign_workspace bytes, 256-byte aligned, same N, D, K).
+ * xgs_vq_stage: writes the bf16 operands of X and of the codebook (E_bf16,
+ * e_norm2 as above) into ws.  xgs_vq_candidates: the MFMA distance sweep;
+ * writes each row's 4 best codewords into ws.  xgs_vq_rescore: FP32 direct
+ * distances of those candidates; writes idx [N] and dist [N]. */
+xgs_status xgs_vq_stage(const float* X, int64_t N, int32_t D, const uint16_t* E_bf16,
+                        const float* e_norm2, int32_t K, void* ws, size_t ws_bytes, xgs_stream_t stream);
+xgs_status xgs_vq_candidates(int64_t N, int32_t D, int32_t K, void* ws, size_t ws_bytes,
+                             xgs_stream_t stream);
+xgs_status xgs_vq_rescore(const float* X, int64_t N, int32_t D, const float* E, int32_t K,
+                          int32_t* idx, float* dist, void* ws, size_t ws_bytes, xgs_stream_t stream);
 
 /* --------------------------------------------------------- a7: EMA update
  * Eq. (ema_update): c_l = #{a_n = l}, s_l = sum_{a_n = l} x_n,

@@ -33,7 +33,8 @@ BWD_ALL, BWD_FEATURES_ONLY = 0, 1
 __all__ = [
     "XgsError", "Gaussians", "Projected", "Binning", "camera", "camera_from", "grid_dims",
     "xgs_project", "xgs_project_posed", "alloc_binning", "xgs_tile_sort", "xgs_render_fwd", "xgs_render_bwd",
-    "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_ema_update", "render",
+    "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_stage", "xgs_vq_candidates", "xgs_vq_rescore",
+    "vq_assign_workspace", "xgs_vq_ema_update", "render",
 ]
 
 
@@ -243,14 +244,43 @@ def xgs_vq_prepare(E: torch.Tensor, E_bf16=None, e_norm2=None, stream=None):
     return E_bf16, e_norm2
 
 
+def vq_assign_workspace(N: int, D: int, K: int, precision: int = VQ_BF16_RESCORE4, device=None) -> torch.Tensor:
+    nbytes = int(lib.xgs_vq_assign_workspace(N, D, K, int(precision)))
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device or "cuda")
+
+
 def xgs_vq_assign(X: torch.Tensor, E: torch.Tensor, E_bf16=None, e_norm2=None, precision: int = VQ_BF16_RESCORE4,
-                  idx=None, dist=None, stream=None):
+                  idx=None, dist=None, workspace=None, stream=None):
     N, D = X.shape
     K = E.shape[0]
     idx = idx if idx is not None else torch.empty(N, dtype=torch.int32, device=X.device)
     dist = dist if dist is not None else torch.empty(N, dtype=torch.float32, device=X.device)
+    if workspace is None:
+        workspace = vq_assign_workspace(N, D, K, precision, X.device)
     check(lib.xgs_vq_assign(_ptr(X), N, D, _ptr(E), _ptr(E_bf16), _ptr(e_norm2), K, int(precision), _ptr(idx),
-                            _ptr(dist), None, 0, _stream(stream)), "xgs_vq_assign")
+                            _ptr(dist), _ptr(workspace), workspace.numel(), _stream(stream)), "xgs_vq_assign")
+    return idx, dist
+
+
+def xgs_vq_stage(X: torch.Tensor, E_bf16: torch.Tensor, e_norm2: torch.Tensor, workspace: torch.Tensor,
+                 stream=None):
+    N, D = X.shape
+    K = E_bf16.shape[0]
+    check(lib.xgs_vq_stage(_ptr(X), N, D, _ptr(E_bf16), _ptr(e_norm2), K, _ptr(workspace), workspace.numel(),
+                           _stream(stream)), "xgs_vq_stage")
+
+
+def xgs_vq_candidates(N: int, D: int, K: int, workspace: torch.Tensor, stream=None):
+    check(lib.xgs_vq_candidates(N, D, K, _ptr(workspace), workspace.numel(), _stream(stream)), "xgs_vq_candidates")
+
+
+def xgs_vq_rescore(X: torch.Tensor, E: torch.Tensor, workspace: torch.Tensor, idx=None, dist=None, stream=None):
+    N, D = X.shape
+    K = E.shape[0]
+    idx = idx if idx is not None else torch.empty(N, dtype=torch.int32, device=X.device)
+    dist = dist if dist is not None else torch.empty(N, dtype=torch.float32, device=X.device)
+    check(lib.xgs_vq_rescore(_ptr(X), N, D, _ptr(E), K, _ptr(idx), _ptr(dist), _ptr(workspace), workspace.numel(),
+                             _stream(stream)), "xgs_vq_rescore")
     return idx, dist
 
 

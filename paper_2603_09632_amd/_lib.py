@@ -67,6 +67,11 @@ SIGNATURES = {
     "xgs_vq_prepare": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "xgs_vq_assign": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_int32,
                                 c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "xgs_vq_stage": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_size_t,
+                               c_void_p]),
+    "xgs_vq_candidates": (c_int32, [c_int64, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
+    "xgs_vq_rescore": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                 c_size_t, c_void_p]),
     "xgs_vq_ema_workspace": (c_size_t, [c_int64, c_int32, c_int32]),
     "xgs_vq_ema_update": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p,
                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float,

@@ -190,6 +190,214 @@ __global__ void __launch_bounds__(64) render_bwd_kernel(
     }
 }
 
+// Matrix-core form.  The walk runs back to front 16 Gaussians at a time.  List
+// entries and splat records are fetched two batches ahead and the batch's
+// channel rows one batch ahead (vector loads into registers, then LDS), so
+// the per-Gaussian work reads only LDS.  Per Gaussian each pixel recovers
+// T_k, forms w_k = a_k T_k and dL/da_k; the six geometric sums (opacity,
+// conic A B C, mean x y) are reduced over the wavefront at once
+// (reduce-scatter, 6 values) and added atomically.  The channel gradients
+// dL/dc_k = sum_p w_k(p) g(p) of the 16 Gaussians are one 16 x 64 x 48
+// product W^T G on v_mfma_f32_16x16x4_f32: W goes through LDS, G (the wave's
+// upstream gradients in operand layout) is loaded once.
+template <int CS, bool GEO, bool EXACT>
+__global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const float4* __restrict__ splat, const float* __restrict__ colors,
+    const float* __restrict__ features, int csem, TileGrid g, const float* __restrict__ d_out,
+    const float* __restrict__ final_T, const int32_t* __restrict__ n_last,
+    float* __restrict__ d_colors, float* __restrict__ d_features, float* __restrict__ d_opacity,
+    float* __restrict__ geo) {
+    constexpr int CH = 4 + CS;
+    constexpr int CHP = (CH + 3) / 4 * 4;           // LDS row stride (float4 rows)
+    constexpr int NT = (CH + 15) / 16;
+    constexpr int PER = (16 * CHP + 63) / 64;       // channel values per lane per batch
+    constexpr int VG = 6;
+    __shared__ float wl[64 * 17];
+    __shared__ float4 rec[16][2];
+    __shared__ int gl[16];
+    __shared__ __align__(16) float chl[16 * CHP];
+    const QuadPix P = quad_pixel(g);
+    if (P.tile >= g.tiles) return;
+    const int lane = threadIdx.x;
+    int my_id = 0;
+    bool my_own = false;
+    if (GEO) rs_layout<VG>(lane, &my_id, &my_own);
+    const size_t hw = (size_t)g.hs * g.ws;
+    const int fstride = EXACT ? CS : csem;
+    const int qx = P.n - (lane & 7), qy = P.m - (lane >> 3);  // quadrant origin
+    // upstream gradients in B-operand layout: pixel 4 kk + lane / 16, channel 16 nt + lane % 16
+    float bg[NT][16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        const int p = 4 * kk + (lane >> 4);
+        const int m = qy + (p >> 3), n = qx + (p & 7);
+        const bool in = m < g.hs && n < g.ws;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int c = 16 * nt + (lane & 15);
+            const bool use = in && c < CH && (GEO || c >= 4) && (EXACT || c < 4 + csem);
+            bg[nt][kk] = use ? d_out[c * hw + (size_t)m * g.ws + n] : 0.f;
+        }
+    }
+    // the pixel's own upstream gradient, for g . c_k
+    float gch[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) gch[c] = 0.f;
+    float T = 1.f;
+    int nl = 0;
+    if (P.inside) {
+        const size_t pix = (size_t)P.m * g.ws + P.n;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gch[c] = GEO ? d_out[c * hw + pix] : 0.f;
+#pragma unroll
+        for (int c = 0; c < CS; ++c)
+            if (EXACT || c < csem) gch[4 + c] = d_out[(4 + c) * hw + pix];
+        T = final_T[pix];
+        nl = n_last[pix];
+    }
+    int jmax = nl;
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1) jmax = max(jmax, __shfl_xor(jmax, k, 64));
+    const uint32_t start = uniform(ranges[2 * P.tile]);
+    const int top = (int)uniform((uint32_t)jmax);
+
+    // prefetch pipeline (lanes 0..15 own one slot each): entries and records
+    // of batches b+1 (arrived) and b+2 (in flight), channel rows of b+1
+    int g1 = -1, g2 = -1;
+    float4 r10 = make_float4(0.f, 0.f, 0.f, 0.f), r11 = r10, r20 = r10, r21 = r10;
+    float cv[PER];
+    auto fetch = [&](int jb, int& gq, float4& q0, float4& q1) {
+        const int j = jb - 1 - lane;
+        gq = -1;
+        if (lane < 16 && j >= 0) {
+            gq = (int)vals[start + j];
+            q0 = splat[2 * (uint32_t)gq];
+            q1 = splat[2 * (uint32_t)gq + 1];
+        }
+    };
+    auto fetch_channels = [&](int gq) {
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int e = lane + 64 * t;
+            const int k = e / CHP, c = e - k * CHP;
+            const int gk = __shfl(gq, k < 16 ? k : 0, 64);
+            cv[t] = (e < 16 * CHP && gk >= 0 && c < CH && (EXACT || c < 4 + csem))
+                        ? channel_of<CS, EXACT>(colors, splat, features, csem, (uint32_t)gk, c) : 0.f;
+        }
+    };
+    fetch(top, g1, r10, r11);
+    fetch_channels(g1);
+    fetch(top - 16, g2, r20, r21);
+    float S = 0.f;
+    for (int jb = top; jb > 0; jb -= 16) {
+        if (lane < 16) {
+            rec[lane][0] = r10;
+            rec[lane][1] = r11;
+            gl[lane] = g1;
+        }
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int e = lane + 64 * t;
+            if (e < 16 * CHP) chl[e] = cv[t];
+        }
+        __syncthreads();
+        g1 = g2; r10 = r20; r11 = r21;
+        fetch_channels(g1);
+        fetch(jb - 32, g2, r20, r21);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int j = jb - 1 - k;
+            float w = 0.f;
+            if (j >= 0) {
+                const float4 s0 = rec[k][0];
+                const float4 s1 = rec[k][1];
+                const int gid = gl[k];
+                const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
+                const bool contrib = j < nl && e.alpha >= kAlphaMin;
+                if (__ballot(contrib) != 0ull) {
+                    float a[VG];
+#pragma unroll
+                    for (int v = 0; v < VG; ++v) a[v] = 0.f;
+                    if (contrib) {
+                        const float om = 1.f - e.alpha;
+                        const float Tk = T / om;
+                        w = e.alpha * Tk;
+                        if (GEO) {
+                            const float4* cr = reinterpret_cast<const float4*>(chl + k * CHP);
+                            float sd = 0.f;
+#pragma unroll
+                            for (int c4 = 0; c4 < CHP / 4; ++c4) {
+                                const float4 v = cr[c4];
+                                if (4 * c4 + 0 < CH) sd += gch[4 * c4 + 0] * v.x;
+                                if (4 * c4 + 1 < CH) sd += gch[4 * c4 + 1] * v.y;
+                                if (4 * c4 + 2 < CH) sd += gch[4 * c4 + 2] * v.z;
+                                if (4 * c4 + 3 < CH) sd += gch[4 * c4 + 3] * v.w;
+                            }
+                            const float dalpha = Tk * sd - S / om;
+                            const bool clamped = !(s1.y * e.G < kAlphaMax);
+                            const float dq = clamped ? 0.f : dalpha * s1.y * e.G * -0.5f;
+                            a[0] = clamped ? 0.f : dalpha * e.G;
+                            a[1] = dq * e.dx * e.dx;
+                            a[2] = 2.f * dq * e.dx * e.dy;
+                            a[3] = dq * e.dy * e.dy;
+                            a[4] = -2.f * dq * (s0.z * e.dx + s0.w * e.dy);
+                            a[5] = -2.f * dq * (s0.w * e.dx + s1.x * e.dy);
+                            S += w * sd;
+                        }
+                        T = Tk;
+                    }
+                    if (GEO) {
+                        reduce_scatter<VG>(a, lane);
+                        if (my_own) {
+                            float* dst;
+                            switch (my_id) {
+                                case 0: dst = d_opacity + gid; break;
+                                case 1: dst = geo + (size_t)gid * GW_STRIDE + GW_A; break;
+                                case 2: dst = geo + (size_t)gid * GW_STRIDE + GW_B; break;
+                                case 3: dst = geo + (size_t)gid * GW_STRIDE + GW_C; break;
+                                case 4: dst = geo + (size_t)gid * GW_STRIDE + GW_MX; break;
+                                default: dst = geo + (size_t)gid * GW_STRIDE + GW_MY; break;
+                            }
+                            unsafeAtomicAdd(dst, a[0]);
+                        }
+                    }
+                }
+            }
+            wl[lane * 17 + k] = w;
+        }
+        __syncthreads();
+        f32x4_t acc[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const float a = wl[(4 * kk + (lane >> 4)) * 17 + (lane & 15)];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = mfma16x16x4(a, bg[nt][kk], acc[nt]);
+        }
+        // acc[nt][r]: Gaussian slot 4 (lane / 16) + r, channel 16 nt + lane % 16
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int gs = gl[4 * (lane >> 4) + r];
+            if (gs < 0) continue;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int c = 16 * nt + (lane & 15);
+                const float v = acc[nt][r];
+                if (c >= CH || v == 0.f) continue;
+                float* dst;
+                if (c < 3) dst = d_colors + 3 * (size_t)gs + c;
+                else if (c == 3) dst = geo + (size_t)gs * GW_STRIDE + GW_DEPTH;
+                else if (EXACT || c - 4 < csem) dst = d_features + (size_t)gs * fstride + (c - 4);
+                else continue;
+                if (GEO || c >= 4) unsafeAtomicAdd(dst, v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 struct CamDevB {
     float fx, fy, limx, limy, near_;
     float R[9], t[3];
@@ -314,9 +522,14 @@ template <int CS, bool GEO, bool EXACT = true>
 static void launch_bwd(const xgs_gaussians* g, const xgs_projected* p, const xgs_binning* b,
                        const TileGrid& tg, const float* d_out, const float* final_T,
                        const int32_t* n_last, xgs_gaussians_grad* gr, float* geo, hipStream_t st) {
-    hipLaunchKernelGGL((render_bwd_kernel<CS, GEO, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
-                       b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
-                       g->c_sem, tg, d_out, final_T, n_last, gr->colors, gr->features, gr->opacity, geo);
+    if (render_variant() == 1)
+        hipLaunchKernelGGL((render_bwd_kernel<CS, GEO, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
+                           b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
+                           g->c_sem, tg, d_out, final_T, n_last, gr->colors, gr->features, gr->opacity, geo);
+    else
+        hipLaunchKernelGGL((render_bwd_mfma_kernel<CS, GEO, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st,
+                           b->ranges, b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
+                           g->c_sem, tg, d_out, final_T, n_last, gr->colors, gr->features, gr->opacity, geo);
 }
 
 template <bool GEO>

@@ -65,13 +65,146 @@ __global__ void __launch_bounds__(64) render_fwd_kernel(
     n_last[pix] = (int32_t)last;
 }
 
+// Matrix-core form.  A wavefront walks its tile list 16 Gaussians at a time.
+// The list entries and splat records of the next batch are fetched by lanes
+// 0..15 with vector loads while the current batch is walked, so the walk
+// reads only LDS (no dependent global load per Gaussian).  For each Gaussian
+// every pixel evaluates alpha and updates T, giving the blend weight
+// w_k(p) = alpha_k T_k (0 for skipped, terminated or absent pairs).  The
+// weights go through LDS (row stride 17: conflict-free both ways) and the
+// channel sums out[p][c] += sum_k w_k(p) chan_k[c] run as a 64 x 16 x 48
+// product on v_mfma_f32_16x16x4_f32, with the channel rows read as vectors
+// (issued before the walk, consumed after it).  The accumulators hold the
+// wave's 64 x (4 + CS) output block until the end.
+template <int CS, bool EXACT>
+__global__ void __launch_bounds__(64) render_fwd_mfma_kernel(
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const float4* __restrict__ splat, const float* __restrict__ colors,
+    const float* __restrict__ features, int csem, TileGrid g, float* __restrict__ out,
+    float* __restrict__ final_T, int32_t* __restrict__ n_last) {
+    constexpr int CH = 4 + CS;
+    constexpr int NT = (CH + 15) / 16;
+    __shared__ float wl[64 * 17];
+    __shared__ float4 rec[16][2];
+    __shared__ int gl[16];
+    const QuadPix P = quad_pixel(g);
+    if (P.tile >= g.tiles) return;
+    const int lane = threadIdx.x;
+    f32x4_t acc[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    float T = 1.f;
+    uint32_t last = 0;
+    bool done = !P.inside;
+    const uint32_t start = uniform(ranges[2 * P.tile]);
+    const uint32_t end = uniform(ranges[2 * P.tile + 1]);
+    // prefetch registers (lanes 0..15): entry and record of the next batch
+    int pg = -1;
+    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
+    auto fetch = [&](uint32_t j0) {
+        const uint32_t j = j0 + (uint32_t)lane;
+        pg = -1;
+        if (lane < 16 && j < end) {
+            pg = (int)vals[j];
+            p0 = splat[2 * (uint32_t)pg];
+            p1 = splat[2 * (uint32_t)pg + 1];
+        }
+    };
+    fetch(start);
+    for (uint32_t j0 = start; j0 < end; j0 += 16) {
+        if (__ballot(!done) == 0ull) break;
+        if (lane < 16) {
+            rec[lane][0] = p0;
+            rec[lane][1] = p1;
+            gl[lane] = pg;
+        }
+        __syncthreads();
+        fetch(j0 + 16);
+        // channel rows of this batch in B-operand layout (consumed after the walk)
+        float b[4][NT];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int gs = gl[4 * kk + (lane >> 4)];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int c = 16 * nt + (lane & 15);
+                b[kk][nt] = (gs >= 0 && c < CH && (EXACT || c < 4 + csem))
+                                ? channel_of<CS, EXACT>(colors, splat, features, csem, (uint32_t)gs, c) : 0.f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t j = j0 + k;
+            float w = 0.f;
+            if (j < end) {
+                const float4 s0 = rec[k][0];
+                const float4 s1 = rec[k][1];
+                const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
+                bool contrib = !done && e.alpha >= kAlphaMin;
+                const float Tn = T * (1.f - e.alpha);
+                if (contrib && Tn < kTStop) {
+                    done = true;
+                    contrib = false;
+                }
+                if (contrib) {
+                    w = e.alpha * T;
+                    T = Tn;
+                    last = j - start + 1;
+                }
+            }
+            wl[lane * 17 + k] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int slot = 4 * kk + (lane >> 4);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const float a = wl[(16 * mt + (lane & 15)) * 17 + slot];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma16x16x4(a, b[kk][nt], acc[mt][nt]);
+            }
+        }
+        __syncthreads();
+    }
+    const size_t hw = (size_t)g.hs * g.ws;
+    if (P.inside) {
+        const size_t pix = (size_t)P.m * g.ws + P.n;
+        final_T[pix] = T;
+        n_last[pix] = (int32_t)last;
+    }
+    // accumulator (mt, nt) holds pixel 16 mt + 4 (lane / 16) + r, channel 16 nt + lane % 16
+    const int qx = P.n - (lane & 7), qy = P.m - (lane >> 3);  // quadrant origin
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 16 * mt + 4 * (lane >> 4) + r;
+            const int m = qy + (p >> 3), n = qx + (p & 7);
+            if (m >= g.hs || n >= g.ws) continue;
+            const size_t pix = (size_t)m * g.ws + n;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int c = 16 * nt + (lane & 15);
+                if (c < CH && (EXACT || c < 4 + csem)) out[c * hw + pix] = acc[mt][nt][r];
+            }
+        }
+}
+
 template <int CS, bool EXACT = true>
 static void launch_fwd(const xgs_gaussians* g, const xgs_projected* p, const xgs_binning* b,
                        const TileGrid& tg, float* out, float* final_T, int32_t* n_last,
                        hipStream_t st) {
-    hipLaunchKernelGGL((render_fwd_kernel<CS, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
-                       b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
-                       g->c_sem, tg, out, final_T, n_last);
+    if (render_variant() == 1)
+        hipLaunchKernelGGL((render_fwd_kernel<CS, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
+                           b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
+                           g->c_sem, tg, out, final_T, n_last);
+    else
+        hipLaunchKernelGGL((render_fwd_mfma_kernel<CS, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
+                           b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
+                           g->c_sem, tg, out, final_T, n_last);
 }
 
 }  // namespace xgs

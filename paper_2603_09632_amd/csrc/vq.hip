@@ -127,211 +127,455 @@ __global__ void __launch_bounds__(256) vq_fp32_kernel(const float* __restrict__ 
 }
 
 // -------------------------------------------------- BF16 MFMA + rescore
-constexpr int B_BM = 64;     // rows per workgroup (resident in LDS)
-constexpr int B_PAD = 8;     // bf16 padding per LDS row (bank spread)
-constexpr int B_FRAGS = 4;   // 32-codeword fragments per wave step (128 codewords)
+//
+// Four kernels.  vq_xprep and vq_eprep lay out bf16 operands with one extra
+// 32-column chunk per row that carries the squared norms:
+//   X row n:     -x^_n, zero padding,  1,  1,  1, h0, h1, h2, 0 ...
+//   codeword c:   e^_c, zero padding, g0, g1, g2,  1,  1,  1, 0 ...
+// with h0 + h1 + h2 = |x^_n|^2 / 2 and g0 + g1 + g2 = |e^_c|^2 / 2 split into
+// three bf16 pieces (exact to about 2^-24 relative), so the plain dot product
+// of the two rows is half the squared distance of the bf16 operands.  The
+// codebook is padded to whole tiles with rows whose g0 is +inf.
+// vq_gemm gives a workgroup 128 rows and one part of the codebook, swept in
+// tiles of 256 codewords.  Both operands go straight from memory into LDS in
+// chunks of 32 columns (direct global->LDS loads, three buffers, issued two
+// chunks ahead) and each of the four wavefronts accumulates a 64-row x
+// 128-codeword block with v_mfma_f32_32x32x16_bf16.  Per row, every lane
+// keeps its 4 smallest as 32-bit rank keys: the value's bits with the lowest
+// seq_bits bits replaced by the candidate's position in the lane's stream
+// (which increases with the codeword index), so ties go to the lower index
+// and an insertion is four min/med3 operations with no branches.  The four
+// lists of a row are merged in LDS.  vq_rescore takes the best 4 over the
+// parts and picks the smallest direct FP32 distance.
+constexpr int Q_BM = 128;                      // rows per workgroup
+constexpr int Q_BN = 256;                      // codewords per tile
+constexpr int Q_BK = 32;                       // bf16 columns per chunk (64 bytes of a row)
+constexpr int Q_XSLOTS = Q_BM * 4;             // 16-byte slots of X per chunk buffer
+constexpr int Q_SLOTS = (Q_BM + Q_BN) * 4;     // slots per chunk buffer
+constexpr int Q_NBUF = 3;
+constexpr int Q_MAX_TILES = 16;                // tiles per part: position fits in 10 bits
+constexpr int Q_MAX_PARTS = 16;                // candidate lists per row in the rescore (x4 <= 64 lanes)
 
-struct Top4 {
-    float s[4];
-    int i[4];
-};
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
 
-// higher score wins; equal scores go to the lower codeword index
-__device__ __forceinline__ bool beats(float s, int i, float os, int oi) {
-    return s > os || (s == os && i < oi);
+// Slot of (row, 16-byte segment) in a chunk buffer.  The XOR spreads the rows
+// that one ds_read_b128 touches (32 rows, fixed segment) over distinct banks.
+__device__ __forceinline__ int q_swz(int row) { return ((row >> 1) ^ (row >> 3)) & 3; }
+__device__ __forceinline__ int q_slot(int row, int seg) { return 4 * row + (seg ^ q_swz(row)); }
+
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+    return (uint32_t)(uintptr_t)(const lds_void_t*)p;
 }
 
-__device__ __forceinline__ void top4_insert(Top4& t, float s, int i) {
-    if (!beats(s, i, t.s[3], t.i[3])) return;
-    t.s[3] = s; t.i[3] = i;
+// LDS fragment read issued as inline asm: the compiler would otherwise wait
+// for every outstanding direct global->LDS load (vmcnt(0)) before it, which
+// serialises the prefetch.  The caller waits on lgkmcnt itself (lds_wait).
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ i32x4_t lds_read16(uint32_t a) {
+    i32x4_t v;
+    asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"(a));
+    return v;
+}
+
+// Waits until at most N LDS operations are outstanding (they complete in
+// order, so the reads of f, issued N operations ago or earlier, are done);
+// the operands tie the fragments to the wait.  N = -1 only ties them (an
+// earlier wait already covered the reads).
+template <int N>
+__device__ __forceinline__ void lds_wait(i32x4_t (&f)[6]) {
+    if constexpr (N == 0)
+        asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(f[0]), "+v"(f[1]), "+v"(f[2]), "+v"(f[3]), "+v"(f[4]), "+v"(f[5]));
+    else if constexpr (N == 6)
+        asm volatile("s_waitcnt lgkmcnt(6)" : "+v"(f[0]), "+v"(f[1]), "+v"(f[2]), "+v"(f[3]), "+v"(f[4]), "+v"(f[5]));
+    else
+        asm volatile("" : "+v"(f[0]), "+v"(f[1]), "+v"(f[2]), "+v"(f[3]), "+v"(f[4]), "+v"(f[5]));
+}
+
+__device__ __forceinline__ int med3i(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
+
+// v = h0 + h1 + h2 with bf16 pieces (each the rounding of what is left).
+__device__ __forceinline__ void split3(float v, uint16_t& h0, uint16_t& h1, uint16_t& h2) {
+    h0 = to_bf16(v);
+    const float r1 = v - from_bf16(h0);
+    h1 = to_bf16(r1);
+    h2 = to_bf16(r1 - from_bf16(h1));
+}
+
+constexpr uint16_t kBf16One = 0x3F80;
+
+// (key, codeword) order: smaller key first, then the lower codeword; empty
+// entries (codeword -1) last.
+__device__ __forceinline__ bool cand_before(int ka, int ca, int kb, int cb) {
+    if (ca < 0) return false;
+    if (cb < 0) return true;
+    return ka < kb || (ka == kb && ca < cb);
+}
+
+
+// One wavefront per row; Dp = D rounded up to 32, row stride Dx = Dp + 32.
+__global__ void __launch_bounds__(256) vq_xprep_kernel(const float* __restrict__ X, int64_t N, int D, int Dp,
+                                                      int Dx, uint16_t* __restrict__ Xa) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= N) return;
+    const f32x4_t* xr = reinterpret_cast<const f32x4_t*>(X + row * D);
+    uint16_t* orow = Xa + row * Dx;
+    uint2* out = reinterpret_cast<uint2*>(orow);
+    float s = 0.f;
+    for (int q = lane; q < Dp / 4; q += 64) {
+        uint2 p = make_uint2(0u, 0u);
+        if (q < D / 4) {
+            const f32x4_t v = __builtin_nontemporal_load(xr + q);
+            uint16_t h[4];
 #pragma unroll
-    for (int k = 3; k > 0; --k) {
-        if (beats(t.s[k], t.i[k], t.s[k - 1], t.i[k - 1])) {
-            float ts = t.s[k]; t.s[k] = t.s[k - 1]; t.s[k - 1] = ts;
-            int ti = t.i[k]; t.i[k] = t.i[k - 1]; t.i[k - 1] = ti;
+            for (int k = 0; k < 4; ++k) {
+                h[k] = to_bf16(v[k]);
+                const float f = from_bf16(h[k]);
+                s += f * f;
+            }
+            p.x = ((uint32_t)h[0] | ((uint32_t)h[1] << 16)) ^ 0x80008000u;  // -x^ (sign flip is exact)
+            p.y = ((uint32_t)h[2] | ((uint32_t)h[3] << 16)) ^ 0x80008000u;
         }
+        out[q] = p;
     }
-}
-
-// NKC > 0: D = 16 * NKC is a compile-time constant and the K loop is fully
-// unrolled (no loop back-edge, so the prefetches stay in flight);
-// NKC == 0: runtime D, rolled loop.
-template <int PF, int NKC>
-__global__ void __launch_bounds__(256) vq_bf16_kernel(const float* __restrict__ X, int64_t N, int D_rt,
-                                                     const float* __restrict__ E,
-                                                     const uint16_t* __restrict__ Eb,
-                                                     const float* __restrict__ en, int K,
-                                                     int32_t* __restrict__ idx, float* __restrict__ dist) {
-    extern __shared__ __align__(16) uint16_t xs[];  // [B_BM][D + B_PAD]
-    const int D = NKC > 0 ? 16 * NKC : D_rt;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int ld = D + B_PAD;
-    const int64_t r0 = (int64_t)blockIdx.x * B_BM;
-    // X rows -> bf16 in LDS (float4 reads along rows)
-    const int q4 = D / 4;
-    for (int e = t; e < B_BM * q4; e += 256) {
-        const int row = e / q4, c4 = e - row * q4;
-        const int64_t gr = r0 + row;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (gr < N) {
-            const f32x4_t q = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t*>(X + gr * D) + c4);
-            v = make_float4(q[0], q[1], q[2], q[3]);
-        }
+    for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
+    if (lane < 8) {
+        uint16_t h0, h1, h2;
+        split3(0.5f * s, h0, h1, h2);
+        uint16_t v[4] = {0, 0, 0, 0};
+        if (lane == 0) { v[0] = kBf16One; v[1] = kBf16One; v[2] = kBf16One; v[3] = h0; }
+        if (lane == 1) { v[0] = h1; v[1] = h2; }
         uint2 p;
-        p.x = (uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16);
-        p.y = (uint32_t)to_bf16(v.z) | ((uint32_t)to_bf16(v.w) << 16);
-        *reinterpret_cast<uint2*>(&xs[row * ld + c4 * 4]) = p;
+        p.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+        p.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+        out[Dp / 4 + lane] = p;
+    }
+}
+
+// One wavefront per (padded) codeword row.
+__global__ void __launch_bounds__(256) vq_eprep_kernel(const uint16_t* __restrict__ Eb, const float* __restrict__ en,
+                                                      int K, int D, int Kp, int Dp, int Dx,
+                                                      uint16_t* __restrict__ Ea) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= Kp) return;
+    const bool real = c < K;
+    uint4* out = reinterpret_cast<uint4*>(Ea + (size_t)c * Dx);
+    const uint4* in = reinterpret_cast<const uint4*>(Eb + (size_t)(real ? c : 0) * D);
+    for (int q = lane; q < Dp / 8; q += 64) out[q] = (real && q < D / 8) ? in[q] : make_uint4(0u, 0u, 0u, 0u);
+    if (lane < 4) {
+        uint16_t g0 = 0x7F80, g1 = 0, g2 = 0;  // +inf: a padded codeword is never chosen
+        if (real) split3(0.5f * en[c], g0, g1, g2);
+        uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (lane == 0) { v[0] = g0; v[1] = g1; v[2] = g2; v[3] = kBf16One; v[4] = kBf16One; v[5] = kBf16One; }
+        uint4 p;
+        p.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+        p.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+        p.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+        p.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+        out[Dp / 8 + lane] = p;
+    }
+}
+
+__global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restrict__ Xa, int64_t N, int Dx,
+                                                        const uint16_t* __restrict__ Ea, int K, int parts,
+                                                        int tiles_part, int seq_bits,
+                                                        int2* __restrict__ cand) {
+    __shared__ __align__(16) uint4 qbuf[Q_NBUF * Q_SLOTS];
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = w & 1, wn = w >> 1;
+    const int64_t blk = blockIdx.x;
+    const int p = (int)(blk % parts);
+    const int64_t r0 = (blk / parts) * Q_BM;
+    const int c_part = p * tiles_part * Q_BN;
+    const int tiles = min(tiles_part, (K - c_part + Q_BN - 1) / Q_BN);
+    const int nkc = Dx / Q_BK;
+    const int total = tiles * nkc;
+    const int rows_here = (int)min((int64_t)Q_BM, N - r0);
+
+    // This wave's direct loads: instruction m fills slots 64 j .. 64 j + 63
+    // of a buffer, j = w + 4 m: X rows 16 j + lane / 4 for m = 0, 1, codeword
+    // rows 16 (w + 4 (m - 2)) + lane / 4 for m = 2..5; lane & 3 is the slot
+    // within the row, holding segment (lane & 3) ^ q_swz(row).  Per-lane byte
+    // offsets are fixed; the chunk moves the (scalar) bases.
+    const int lr = lane >> 2;
+    const char* xbase = reinterpret_cast<const char*>(Xa + r0 * Dx);
+    const char* ebase = reinterpret_cast<const char*>(Ea + (size_t)c_part * Dx);
+    uint32_t xoff[2], eoff[4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int row = 16 * (w + 4 * m) + lr;
+        const int rc = row < rows_here ? row : rows_here - 1;
+        xoff[m] = (uint32_t)rc * (uint32_t)(2 * Dx) + 16u * (uint32_t)((lane & 3) ^ q_swz(row));
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int row = 16 * (w + 4 * m) + lr;
+        eoff[m] = (uint32_t)row * (uint32_t)(2 * Dx) + 16u * (uint32_t)((lane & 3) ^ q_swz(row));
+    }
+    // next chunk to issue: tile, chunk within the tile, buffer
+    int n_tl = 0, n_kc = 0, n_b = 0;
+    auto issue = [&]() {
+        const int tl = n_tl, kc = n_kc;
+        uint4* dst = qbuf + n_b * Q_SLOTS;
+        if (++n_kc == nkc) { n_kc = 0; ++n_tl; }
+        n_b = n_b == Q_NBUF - 1 ? 0 : n_b + 1;
+        const char* xb = xbase + kc * 64;
+        const char* eb = ebase + ((size_t)tl * Q_BN * Dx + (size_t)kc * Q_BK) * 2;
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(xb + xoff[m]), (lds_void_t*)(dst + 64 * (w + 4 * m)), 16,
+                                             0, 0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(eb + eoff[m]),
+                                             (lds_void_t*)(dst + Q_XSLOTS + 64 * (w + 4 * m)), 16, 0, 0);
+    };
+
+    // Fragment addresses: X fragment jx covers rows wm 64 + 32 jx + lane % 32,
+    // codeword fragment i rows wn 128 + 32 i + lane % 32; step ks reads
+    // segment 2 ks + lane / 32.  Rows 32 apart share the swizzle, so the
+    // fragments of one step are 128 slots (2048 bytes) apart.
+    const int fr = lane & 31, hf = lane >> 5;
+    const uint32_t qb0 = lds_addr(qbuf);
+    uint32_t xa[2], ea[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        xa[ks] = qb0 + 16u * (uint32_t)q_slot(wm * 64 + fr, 2 * ks + hf);
+        ea[ks] = qb0 + 16u * (uint32_t)(Q_XSLOTS + q_slot(wn * 128 + fr, 2 * ks + hf));
+    }
+    auto read_frags = [&](int b, int ks, i32x4_t (&f)[6]) {
+        const uint32_t o = (uint32_t)(b * Q_SLOTS * 16);
+        f[0] = lds_read16(xa[ks] + o);
+        f[1] = lds_read16(xa[ks] + o + 2048u);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[2 + i] = lds_read16(ea[ks] + o + 2048u * i);
+    };
+
+    // accumulator r of codeword fragment i holds codeword
+    // tile base + wn 128 + 32 i + 8 (r / 4) + 4 hf + r % 4, row 32 jx + fr
+    f32x16_t acc[4][2];
+    int top[2][4];
+#pragma unroll
+    for (int jx = 0; jx < 2; ++jx)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) top[jx][q] = 0x7FFFFFFF;
+    const uint32_t keep = ~((1u << seq_bits) - 1u);
+    auto tile_top4 = [&](int tl) {
+#pragma unroll
+        for (int jx = 0; jx < 2; ++jx)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int k = (int)((__float_as_uint(acc[i][jx][r]) & keep) |
+                                        (uint32_t)((tl << 6) | (i << 4) | r));
+                    top[jx][3] = med3i(top[jx][2], top[jx][3], k);
+                    top[jx][2] = med3i(top[jx][1], top[jx][2], k);
+                    top[jx][1] = med3i(top[jx][0], top[jx][1], k);
+                    top[jx][0] = min(top[jx][0], k);
+                }
+    };
+    auto mfma_step = [&](const i32x4_t (&f)[6]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int jx = 0; jx < 2; ++jx)
+                acc[i][jx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, f[2 + i]),
+                                                                    __builtin_bit_cast(bf16x8_t, f[jx]),
+                                                                    acc[i][jx], 0, 0, 0);
+    };
+    auto mfma_first = [&](const i32x4_t (&f)[6]) {
+        const f32x16_t z = {};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int jx = 0; jx < 2; ++jx)
+                acc[i][jx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, f[2 + i]),
+                                                                    __builtin_bit_cast(bf16x8_t, f[jx]), z, 0,
+                                                                    0, 0);
+    };
+
+    // prologue: chunks 0 and 1 in flight, wait for chunk 0
+    issue();
+    if (total > 1) {
+        issue();
+        asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+    } else {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    __builtin_amdgcn_s_barrier();
+    if (total > 2) issue();
+    i32x4_t f0[6], f1[6];
+    read_frags(0, 0, f0);
+    int g = 0, b = 0;
+    for (int tl = 0; tl < tiles; ++tl) {
+        for (int kc = 0; kc < nkc; ++kc, ++g) {
+            const int bn = b == Q_NBUF - 1 ? 0 : b + 1;
+            read_frags(b, 1, f1);
+            lds_wait<6>(f0);  // f0 was read before f1's six reads
+            if (kc == 0) mfma_first(f0);
+            else mfma_step(f0);
+            // chunk g + 1 must have landed (own loads, then everyone's); chunk
+            // g + 2 may still be in flight.  All reads of buffer b are
+            // complete (lgkmcnt(0)), so after the barrier it can be refilled.
+            if (g + 2 < total) {
+                asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)" ::: "memory");
+            } else {
+                asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+            }
+            __builtin_amdgcn_s_barrier();
+            if (g + 3 < total) issue();
+            if (g + 1 < total) read_frags(bn, 0, f0);
+            lds_wait<-1>(f1);  // complete since the lgkmcnt(0) above
+            mfma_step(f1);
+            b = bn;
+        }
+        tile_top4(tl);
     }
     __syncthreads();
 
-    Top4 top[2];
+    // merge: row (0..127) x 4 lists (wn, hf) x 4 candidates
+    int2* mc = reinterpret_cast<int2*>(qbuf);
+    const uint32_t pos_mask = (1u << seq_bits) - 1u;
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int jx = 0; jx < 2; ++jx) {
+        const int row = wm * 64 + 32 * jx + fr;
+        const int list = 2 * wn + hf;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) { top[h].s[k] = -INFINITY; top[h].i[k] = 0x7FFFFFFF; }
-
-    const int col = lane & 31, half = lane >> 5;
-    const uint16_t* xrow0 = xs + col * ld + 8 * half;
-    const uint16_t* xrow1 = xs + (32 + col) * ld + 8 * half;
-    const int per_wave = (K + 3) / 4;  // codewords swept by this wave: [w*per_wave, ...)
-    const int cw0 = w * per_wave, cw1 = min(K, cw0 + per_wave);
-    const int nk = D / 16;
-    for (int c0 = cw0; c0 < cw1; c0 += 32 * B_FRAGS) {
-        f32x16_t acc[B_FRAGS][2];
-        const uint16_t* arow[B_FRAGS];
-#pragma unroll
-        for (int f = 0; f < B_FRAGS; ++f) {
-            const int cbase = c0 + 32 * f;
-#pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int c = cbase + 8 * g4 + 4 * half + r;
-                    const float v = en[min(c, K - 1)];
-                    const float init = c < cw1 ? -0.5f * v : -INFINITY;
-                    acc[f][0][4 * g4 + r] = init;
-                    acc[f][1][4 * g4 + r] = init;
-                }
-            }
-            arow[f] = Eb + (size_t)min(cbase + col, K - 1) * D + 8 * half;
-        }
-        // A fragments are loaded PF k-steps ahead of their use, the X
-        // fragments from LDS one step ahead.
-        bf16x8_t abuf[PF][B_FRAGS];
-#pragma unroll
-        for (int s = 0; s < PF; ++s)
-#pragma unroll
-            for (int f = 0; f < B_FRAGS; ++f)
-                abuf[s][f] = *reinterpret_cast<const bf16x8_t*>(arow[f] + 16 * min(s, nk - 1));
-        bf16x8_t b0 = *reinterpret_cast<const bf16x8_t*>(xrow0);
-        bf16x8_t b1 = *reinterpret_cast<const bf16x8_t*>(xrow1);
-        // nk is a multiple of PF (the host picks PF accordingly)
-#pragma unroll
-        for (int k = 0; k < (NKC > 0 ? NKC : nk); k += PF) {
-#pragma unroll
-            for (int s = 0; s < PF; ++s) {
-                const int kk = k + s;
-                const int kb = min(kk + 1, nk - 1);
-                const bf16x8_t nb0 = *reinterpret_cast<const bf16x8_t*>(xrow0 + 16 * kb);
-                const bf16x8_t nb1 = *reinterpret_cast<const bf16x8_t*>(xrow1 + 16 * kb);
-#pragma unroll
-                for (int f = 0; f < B_FRAGS; ++f) {
-                    acc[f][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abuf[s][f], b0, acc[f][0], 0, 0, 0);
-                    acc[f][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abuf[s][f], b1, acc[f][1], 0, 0, 0);
-                }
-                const int kn = min(kk + PF, nk - 1);
-#pragma unroll
-                for (int f = 0; f < B_FRAGS; ++f)
-                    abuf[s][f] = *reinterpret_cast<const bf16x8_t*>(arow[f] + 16 * kn);
-                b0 = nb0;
-                b1 = nb1;
-                // keep the prefetches where they are: the scheduler would
-                // otherwise sink them next to their use, PF steps later
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-        // top-4 per row: candidates i = c0 + 32 f + 8 (r/4) + 4 half + r%4
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            float mx = -INFINITY;
-#pragma unroll
-            for (int f = 0; f < B_FRAGS; ++f)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) mx = fmaxf(mx, acc[f][h][r]);
-            if (mx >= top[h].s[3]) {
-#pragma unroll
-                for (int f = 0; f < B_FRAGS; ++f)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int c = c0 + 32 * f + 8 * (r >> 2) + 4 * half + (r & 3);
-                        top4_insert(top[h], acc[f][h][r], c);
-                    }
-            }
-        }
-    }
-    __syncthreads();  // X tile no longer needed: reuse LDS for candidates
-    // candidate lists: row (0..63) x 8 lists (4 waves x 2 halves) x 4
-    float* cs = reinterpret_cast<float*>(xs);
-    int* ci = reinterpret_cast<int*>(cs + B_BM * 32);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int row = 32 * h + col;
-        const int list = 2 * w + half;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            cs[row * 32 + list * 4 + k] = top[h].s[k];
-            ci[row * 32 + list * 4 + k] = top[h].i[k];
+        for (int q = 0; q < 4; ++q) {
+            const int k = top[jx][q];
+            const uint32_t s = (uint32_t)k & pos_mask;
+            const int c = c_part + (int)(s >> 6) * Q_BN + wn * 128 + 32 * (int)((s >> 4) & 3) +
+                          8 * (int)((s >> 2) & 3) + 4 * hf + (int)(s & 3);
+            const bool ok = k != 0x7FFFFFFF && c < K;
+            mc[row * 16 + list * 4 + q] = make_int2(ok ? (int)((uint32_t)k & keep) : 0x7FFFFFFF, ok ? c : -1);
         }
     }
     __syncthreads();
-    // each wave takes 16 rows; per row, lane k < 32 holds one candidate
-    for (int rr = 0; rr < 16; ++rr) {
-        const int row = 16 * w + rr;
-        const int64_t gr = r0 + row;
-        float s = lane < 32 ? cs[row * 32 + lane] : -INFINITY;
-        int ii = lane < 32 ? ci[row * 32 + lane] : 0x7FFFFFFF;
-        // pick the 4 best of the 32 by repeated arg-max
-        int pick[4];
+    if (t < rows_here) {
+        int bk[4] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
+        int bc[4] = {-1, -1, -1, -1};
+        for (int e = 0; e < 16; ++e) {
+            const int2 v = mc[t * 16 + e];
+            int k = v.x, c = v.y;
+            // carry the entry up the sorted list (static indices: registers)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float bs = s;
-            int bi = ii;
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const float os = __shfl_xor(bs, o, 64);
-                const int oi = __shfl_xor(bi, o, 64);
-                if (beats(os, oi, bs, bi)) { bs = os; bi = oi; }
-            }
-            pick[k] = bi;
-            if (ii == bi) { s = -INFINITY; ii = 0x7FFFFFFF; }
+            for (int q = 3; q >= 0; --q)
+                if (cand_before(k, c, bk[q], bc[q])) {
+                    const int tk = bk[q], tc = bc[q];
+                    bk[q] = k; bc[q] = c; k = tk; c = tc;
+                }
         }
-        if (gr >= N) continue;  // uniform per wave
-        // FP32 rescore of the 4 picks, lanes across D
-        const float* xr = X + gr * D;
-        float part[4] = {0.f, 0.f, 0.f, 0.f};
+        int2* out = cand + ((r0 + t) * parts + p) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = make_int2(bk[q], bc[q]);
+    }
+}
+
+template <bool V4>
+__global__ void __launch_bounds__(256) vq_rescore_kernel(const float* __restrict__ X, int64_t N, int D,
+                                                        const float* __restrict__ E, int K,
+                                                        const int2* __restrict__ cand, int parts,
+                                                        int32_t* __restrict__ idx, float* __restrict__ dist) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= N) return;  // uniform per wave
+    const int nc = 4 * parts;
+    int2 v = lane < nc ? cand[row * nc + lane] : make_int2(0x7FFFFFFF, -1);
+    int ck = v.x, cc = v.y;
+    int pick[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int bk = ck, bc = cc;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const int ok = __shfl_xor(bk, o, 64), oc = __shfl_xor(bc, o, 64);
+            if (cand_before(ok, oc, bk, bc)) { bk = ok; bc = oc; }
+        }
+        pick[q] = bc;
+        if (cc == bc) cc = -1;  // codewords are distinct across lists
+    }
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
+    const float* xr = X + row * D;
+    const float* er[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) er[q] = E + (size_t)(pick[q] >= 0 ? pick[q] : 0) * D;
+    if constexpr (V4) {
+        for (int d4 = lane; d4 < D / 4; d4 += 64) {
+            const f32x4_t xv = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t*>(xr) + d4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const f32x4_t ev = reinterpret_cast<const f32x4_t*>(er[q])[d4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float df = xv[k] - ev[k];
+                    part[q] += df * df;
+                }
+            }
+        }
+    } else {
         for (int d = lane; d < D; d += 64) {
             const float xv = xr[d];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int c = pick[k] < K ? pick[k] : K - 1;
-                const float df = xv - E[(size_t)c * D + d];
-                part[k] += df * df;
+            for (int q = 0; q < 4; ++q) {
+                const float df = xv - er[q][d];
+                part[q] += df * df;
             }
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) part[k] += __shfl_xor(part[k], o, 64);
-        if (lane == 0) {
-            float bd = INFINITY;
-            int bi = 0x7FFFFFFF;
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (pick[k] < K && better(part[k], pick[k], bd, bi)) { bd = part[k]; bi = pick[k]; }
-            idx[gr] = bi;
-            dist[gr] = bd;
-        }
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) part[q] += __shfl_xor(part[q], o, 64);
+    if (lane == 0) {
+        float bd = INFINITY;
+        int bi = 0x7FFFFFFF;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (pick[q] >= 0 && better(part[q], pick[q], bd, bi)) { bd = part[q]; bi = pick[q]; }
+        idx[row] = bi;
+        dist[row] = bd;
+    }
+}
+
+struct VqWs {
+    uint16_t* xa;
+    uint16_t* ea;
+    int2* cand;
+};
+
+struct VqPlan {
+    int tiles, tiles_part, parts, seq_bits;
+};
+
+static VqPlan vq_plan(int K) {
+    VqPlan p;
+    p.tiles = (K + Q_BN - 1) / Q_BN;
+    p.parts = (p.tiles + Q_MAX_TILES - 1) / Q_MAX_TILES;
+    p.tiles_part = (p.tiles + p.parts - 1) / p.parts;
+    p.parts = (p.tiles + p.tiles_part - 1) / p.tiles_part;
+    int b = 0;
+    while ((1 << b) < p.tiles_part) ++b;
+    p.seq_bits = 6 + b;
+    return p;
+}
+
+static int vq_dp(int D) { return (D + Q_BK - 1) / Q_BK * Q_BK; }
+
+static VqWs carve_vq(void* base, int64_t N, int D, const VqPlan& plan, size_t* bytes) {
+    Carve c(base);
+    VqWs w;
+    const int64_t n1 = N > 0 ? N : 1;
+    const size_t dx = (size_t)vq_dp(D) + Q_BK;
+    w.xa = c.take<uint16_t>((size_t)n1 * dx);
+    w.ea = c.take<uint16_t>((size_t)plan.parts * plan.tiles_part * Q_BN * dx);
+    w.cand = c.take<int2>((size_t)n1 * plan.parts * 4);
+    *bytes = c.total();
+    return w;
 }
 
 // ------------------------------------------------------------------- EMA
@@ -491,8 +735,10 @@ static int bits_for(int64_t k) {
 using namespace xgs;
 
 extern "C" size_t xgs_vq_assign_workspace(int64_t N, int32_t D, int32_t K, int32_t precision) {
-    (void)N; (void)D; (void)K; (void)precision;
-    return 0;
+    if (precision != XGS_VQ_BF16_RESCORE4 || D < 1 || K < 1) return 0;
+    size_t bytes = 0;
+    carve_vq(nullptr, N < 0 ? 0 : N, D, vq_plan(K), &bytes);
+    return bytes;
 }
 
 extern "C" xgs_status xgs_vq_prepare(const float* E, int32_t K, int32_t D, uint16_t* E_bf16,
@@ -505,59 +751,99 @@ extern "C" xgs_status xgs_vq_prepare(const float* E, int32_t K, int32_t D, uint1
     return check_launch("xgs_vq_prepare");
 }
 
+// Checks the BF16 sizes and carves the workspace.
+static xgs_status vq_bf16_setup(const char* who, int64_t N, int32_t D, int32_t K, void* ws, size_t ws_bytes,
+                                VqPlan* plan, VqWs* w) {
+    if (N < 0 || D < 1 || K < 1) return fail(XGS_ERR_INVALID_ARG, std::string(who) + ": bad sizes");
+    if (D % 8 != 0) return fail(XGS_ERR_UNSUPPORTED, std::string(who) + ": BF16 path needs D % 8 == 0");
+    if (N > (int64_t)1 << 40) return fail(XGS_ERR_UNSUPPORTED, std::string(who) + ": N too large");
+    *plan = vq_plan(K);
+    if (plan->parts > Q_MAX_PARTS) return fail(XGS_ERR_UNSUPPORTED, std::string(who) + ": K above 65536");
+    const int64_t dx = vq_dp(D) + Q_BK;
+    if ((int64_t)plan->parts * plan->tiles_part * Q_BN * dx >= ((int64_t)1 << 31) || Q_BM * dx >= ((int64_t)1 << 30))
+        return fail(XGS_ERR_UNSUPPORTED, std::string(who) + ": codebook above 2^31 bf16 elements");
+    if ((N + Q_BM - 1) / Q_BM * plan->parts >= ((int64_t)1 << 31))
+        return fail(XGS_ERR_UNSUPPORTED, std::string(who) + ": N too large");
+    if (!aligned(ws, 256)) return fail(XGS_ERR_INVALID_ARG, std::string(who) + ": workspace must be 256-byte aligned");
+    size_t need = 0;
+    *w = carve_vq(ws, N, D, *plan, &need);
+    if (!ws || ws_bytes < need) return fail(XGS_ERR_CAPACITY, std::string(who) + ": workspace too small");
+    return XGS_OK;
+}
+
+extern "C" xgs_status xgs_vq_stage(const float* X, int64_t N, int32_t D, const uint16_t* E_bf16,
+                                   const float* e_norm2, int32_t K, void* ws, size_t ws_bytes,
+                                   xgs_stream_t stream) {
+    clear_error();
+    VqPlan plan;
+    VqWs w;
+    if (xgs_status s = vq_bf16_setup("xgs_vq_stage", N, D, K, ws, ws_bytes, &plan, &w)) return s;
+    if ((N > 0 && !X) || !E_bf16 || !e_norm2) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_stage: null pointer");
+    if (!aligned(X, 16) || !aligned(E_bf16, 16))
+        return fail(XGS_ERR_INVALID_ARG, "xgs_vq_stage: X and E_bf16 must be 16-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    const int Dp = vq_dp(D), Dx = Dp + Q_BK;
+    const int Kp = plan.parts * plan.tiles_part * Q_BN;
+    if (N > 0)
+        hipLaunchKernelGGL(vq_xprep_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X, N, D, Dp, Dx, w.xa);
+    hipLaunchKernelGGL(vq_eprep_kernel, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, st, E_bf16, e_norm2, K, D, Kp,
+                       Dp, Dx, w.ea);
+    return check_launch("xgs_vq_stage");
+}
+
+extern "C" xgs_status xgs_vq_candidates(int64_t N, int32_t D, int32_t K, void* ws, size_t ws_bytes,
+                                        xgs_stream_t stream) {
+    clear_error();
+    VqPlan plan;
+    VqWs w;
+    if (xgs_status s = vq_bf16_setup("xgs_vq_candidates", N, D, K, ws, ws_bytes, &plan, &w)) return s;
+    if (N == 0) return XGS_OK;
+    const int64_t blocks = (N + Q_BM - 1) / Q_BM * plan.parts;
+    hipLaunchKernelGGL(vq_gemm_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, w.xa, N,
+                       vq_dp(D) + Q_BK, w.ea, K, plan.parts, plan.tiles_part, plan.seq_bits, w.cand);
+    return check_launch("xgs_vq_candidates");
+}
+
+extern "C" xgs_status xgs_vq_rescore(const float* X, int64_t N, int32_t D, const float* E, int32_t K,
+                                     int32_t* idx, float* dist, void* ws, size_t ws_bytes, xgs_stream_t stream) {
+    clear_error();
+    VqPlan plan;
+    VqWs w;
+    if (xgs_status s = vq_bf16_setup("xgs_vq_rescore", N, D, K, ws, ws_bytes, &plan, &w)) return s;
+    if (N == 0) return XGS_OK;
+    if (!X || !E || !idx || !dist) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_rescore: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned blocks = (unsigned)((N + 3) / 4);
+    if (D % 4 == 0 && aligned(X, 16) && aligned(E, 16))
+        hipLaunchKernelGGL(vq_rescore_kernel<true>, dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand, plan.parts,
+                           idx, dist);
+    else
+        hipLaunchKernelGGL(vq_rescore_kernel<false>, dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand,
+                           plan.parts, idx, dist);
+    return check_launch("xgs_vq_rescore");
+}
+
 extern "C" xgs_status xgs_vq_assign(const float* X, int64_t N, int32_t D, const float* E,
                                     const uint16_t* E_bf16, const float* e_norm2, int32_t K,
                                     int32_t precision, int32_t* idx, float* dist, void* ws,
                                     size_t ws_bytes, xgs_stream_t stream) {
-    (void)ws; (void)ws_bytes;
     clear_error();
     if (N < 0 || D < 1 || K < 1) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_assign: bad sizes");
+    if (precision != XGS_VQ_FP32 && precision != XGS_VQ_BF16_RESCORE4)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_vq_assign: unknown precision");
     if (N == 0) return XGS_OK;
     if (!X || !E || !idx || !dist) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_assign: null pointer");
     if (N > (int64_t)1 << 40) return fail(XGS_ERR_UNSUPPORTED, "xgs_vq_assign: N too large");
-    hipStream_t st = (hipStream_t)stream;
     if (precision == XGS_VQ_FP32) {
         const int64_t blocks = (N + P_BM - 1) / P_BM;
-        hipLaunchKernelGGL(vq_fp32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X, N, D, E, K, idx, dist);
+        hipLaunchKernelGGL(vq_fp32_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, X, N, D, E, K,
+                           idx, dist);
         return check_launch("xgs_vq_assign fp32");
     }
-    if (precision != XGS_VQ_BF16_RESCORE4) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_assign: unknown precision");
     if (!E_bf16 || !e_norm2) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_assign: bf16 shadow or norms missing");
-    if (D % 16 != 0) return fail(XGS_ERR_UNSUPPORTED, "xgs_vq_assign: BF16 path needs D % 16 == 0");
-    if (!aligned(X, 16) || !aligned(E_bf16, 16) || !aligned(e_norm2, 16))
-        return fail(XGS_ERR_INVALID_ARG, "xgs_vq_assign: X, E_bf16, e_norm2 must be 16-byte aligned");
-    const size_t lds = (size_t)B_BM * (D + B_PAD) * sizeof(uint16_t);
-    const size_t lds_cand = (size_t)B_BM * 32 * 8;
-    const size_t lds_bytes = lds > lds_cand ? lds : lds_cand;
-    if (lds_bytes > 160 * 1024) return fail(XGS_ERR_UNSUPPORTED, "xgs_vq_assign: D too large for the LDS-resident row tile");
-    const int64_t blocks = (N + B_BM - 1) / B_BM;
-    const int nk = D / 16;
-    const void* fn;
-    void (*launch)(dim3, size_t, hipStream_t, const float*, int64_t, int, const float*, const uint16_t*,
-                   const float*, int, int32_t*, float*);
-#define XGS_VQ_KERNEL(PF, NKC)                                                                          \
-    fn = (const void*)vq_bf16_kernel<PF, NKC>;                                                          \
-    launch = [](dim3 g, size_t l, hipStream_t s, const float* X_, int64_t N_, int D_, const float* E_,  \
-                const uint16_t* Eb_, const float* en_, int K_, int32_t* i_, float* d_) {                \
-        hipLaunchKernelGGL((vq_bf16_kernel<PF, NKC>), g, dim3(256), l, s, X_, N_, D_, E_, Eb_, en_, K_, \
-                           i_, d_);                                                                      \
-    };
-    switch (nk) {
-        case 48: XGS_VQ_KERNEL(4, 48) break;
-        case 32: XGS_VQ_KERNEL(4, 32) break;
-        case 16: XGS_VQ_KERNEL(4, 16) break;
-        case 8: XGS_VQ_KERNEL(4, 8) break;
-        case 4: XGS_VQ_KERNEL(4, 4) break;
-        default:
-            if (nk % 4 == 0) { XGS_VQ_KERNEL(4, 0) }
-            else if (nk % 2 == 0) { XGS_VQ_KERNEL(2, 0) }
-            else { XGS_VQ_KERNEL(1, 0) }
-    }
-#undef XGS_VQ_KERNEL
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess)
-        return fail(XGS_ERR_HIP, "xgs_vq_assign: cannot reserve " + std::to_string(lds_bytes) + " bytes of LDS");
-    launch(dim3((unsigned)blocks), lds_bytes, st, X, N, D, E, E_bf16, e_norm2, K, idx, dist);
-    return check_launch("xgs_vq_assign bf16");
+    if (xgs_status s = xgs_vq_stage(X, N, D, E_bf16, e_norm2, K, ws, ws_bytes, stream)) return s;
+    if (xgs_status s = xgs_vq_candidates(N, D, K, ws, ws_bytes, stream)) return s;
+    return xgs_vq_rescore(X, N, D, E, K, idx, dist, ws, ws_bytes, stream);
 }
 
 extern "C" size_t xgs_vq_ema_workspace(int64_t N, int32_t D, int32_t K) {

@@ -76,3 +76,5 @@ def test_workspace_queries_grow_with_size(xgs):
     assert 0 < a < b
     assert lib.xgs_render_bwd_workspace(1_000_000) >= 32_000_000
     assert lib.xgs_vq_ema_workspace(816_000, 768, 4096) > 816_000 * 24
+    assert lib.xgs_vq_assign_workspace(816_000, 768, 4096, 0) == 0
+    assert lib.xgs_vq_assign_workspace(816_000, 768, 4096, 1) >= 816_000 * 800 * 2

@@ -61,7 +61,8 @@ def vq_case(n, d, k, clusters, seed=2):
     return X, E
 
 
-@pytest.mark.parametrize("n,d,k", [(12_288, 64, 128), (1000, 48, 77), (65, 16, 5)])
+@pytest.mark.parametrize("n,d,k", [(12_288, 64, 128), (1000, 48, 77), (65, 16, 5), (3000, 72, 5000), (300, 8, 1),
+                                   (4500, 32, 700)])
 def test_vq_assign_small(xgs, n, d, k):
     X, E = vq_case(n, d, k, 16)
     ri, d1, d2 = oracle.vq_assign(X, E)
@@ -77,6 +78,25 @@ def test_vq_assign_small(xgs, n, d, k):
         assert rel_max(np_(dist), chosen) < 1e-5
     if n == 12_288:
         assert raw >= 0.999
+
+
+def test_vq_staged_calls_equal_assign(xgs):
+    """xgs_vq_stage -> xgs_vq_candidates -> xgs_vq_rescore is xgs_vq_assign
+    (bitwise), with K spanning two codebook parts and a ragged row tail."""
+    X, E = vq_case(2_000 + 37, 40, 4_400, 32, seed=12)
+    Xg, Eg = t(X), t(E)
+    Eb, en = xgs.xgs_vq_prepare(Eg)
+    idx_a, dist_a = xgs.xgs_vq_assign(Xg, Eg, Eb, en, xgs.VQ_BF16_RESCORE4)
+    ws = xgs.vq_assign_workspace(len(X), 40, 4_400)
+    xgs.xgs_vq_stage(Xg, Eb, en, ws)
+    xgs.xgs_vq_candidates(len(X), 40, 4_400, ws)
+    idx_s, dist_s = xgs.xgs_vq_rescore(Xg, Eg, ws)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(np_(idx_a), np_(idx_s))
+    np.testing.assert_array_equal(np_(dist_a), np_(dist_s))
+    ri, d1, d2 = oracle.vq_assign(X, E)
+    raw, adj = agreement(np_(idx_s), ri, d1, d2)
+    assert adj >= 0.999, (raw, adj)
 
 
 def test_vq_prepare_is_bf16_rounding(xgs):
