@@ -1,6 +1,4 @@
 // Status strings, the thread-local error text and camera validation.
-#include <cstdlib>
-
 #include "common.h"
 #include "render_common.h"
 
@@ -23,14 +21,6 @@ xgs_status validate_camera(const xgs_camera* c) {
     if ((int64_t)g.tx * g.ty >= (int64_t(1) << 31))
         return fail(XGS_ERR_UNSUPPORTED, "camera: too many tiles");
     return XGS_OK;
-}
-
-int render_variant() {
-    static const int v = [] {
-        const char* e = std::getenv("XGS_RENDER_VARIANT");
-        return (e && e[0] == '1') ? 1 : 2;
-    }();
-    return v;
 }
 
 }  // namespace xgs

@@ -83,114 +83,7 @@ __device__ __forceinline__ void rs_layout(int lane, int* out_id, bool* out_own) 
     *out_own = own[0];
 }
 
-// Value layout per Gaussian: [0,3) rgb, 3 depth, [4, 4+CS) semantic, then
-// (GEO only) opacity, A, B, C, mean x, mean y.
-template <int CS, bool GEO, bool EXACT>
-__global__ void __launch_bounds__(64) render_bwd_kernel(
-    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
-    const float4* __restrict__ splat, const float* __restrict__ colors,
-    const float* __restrict__ features, int csem, TileGrid g, const float* __restrict__ d_out,
-    const float* __restrict__ final_T, const int32_t* __restrict__ n_last,
-    float* __restrict__ d_colors, float* __restrict__ d_features, float* __restrict__ d_opacity,
-    float* __restrict__ geo) {
-    const QuadPix P = quad_pixel(g);
-    if (P.tile >= g.tiles) return;
-    constexpr int CH = 4 + CS;
-    constexpr int V = GEO ? CH + 6 : CS;
-    const int lane = threadIdx.x;
-    int my_id;
-    bool my_own;
-    rs_layout<V>(lane, &my_id, &my_own);
-
-    const size_t hw = (size_t)g.hs * g.ws, pix = (size_t)P.m * g.ws + P.n;
-    float gch[CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) gch[c] = 0.f;
-    float T = 1.f;
-    int nl = 0;
-    if (P.inside) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) gch[c] = GEO ? d_out[c * hw + pix] : 0.f;
-#pragma unroll
-        for (int c = 0; c < CS; ++c)
-            if (EXACT || c < csem) gch[4 + c] = d_out[(4 + c) * hw + pix];
-        T = final_T[pix];
-        nl = n_last[pix];
-    }
-    int jmax = nl;
-#pragma unroll
-    for (int k = 32; k >= 1; k >>= 1) jmax = max(jmax, __shfl_xor(jmax, k, 64));
-    const uint32_t start = uniform(ranges[2 * P.tile]);
-    const int top = (int)uniform((uint32_t)jmax);
-    float S = 0.f;
-    for (int j = top - 1; j >= 0; --j) {
-        const uint32_t gid = uniform(vals[start + j]);
-        const float4 s0 = splat[2 * gid];
-        const float4 s1 = splat[2 * gid + 1];
-        const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
-        const bool contrib = j < nl && e.alpha >= kAlphaMin;
-        if (__ballot(contrib) == 0ull) continue;
-        const float* col = colors + 3 * (size_t)gid;
-        const int fstride = EXACT ? CS : csem;
-        const float* f = features + (size_t)gid * fstride;
-        float a[V];
-        if (contrib) {
-            const float om = 1.f - e.alpha;
-            const float Tk = T / om;
-            const float w = e.alpha * Tk;
-            float s = 0.f;
-            if (GEO) {
-                s = gch[0] * col[0] + gch[1] * col[1] + gch[2] * col[2] + gch[3] * s1.z;
-            }
-#pragma unroll
-            for (int c = 0; c < CS; ++c)
-                if (EXACT || c < csem) s += gch[4 + c] * f[c];
-            if (GEO) {
-#pragma unroll
-                for (int c = 0; c < CH; ++c) a[c] = w * gch[c];
-                const float dalpha = Tk * s - S / om;
-                const bool clamped = !(s1.y * e.G < kAlphaMax);
-                const float dq = clamped ? 0.f : dalpha * s1.y * e.G * -0.5f;
-                a[CH + 0] = clamped ? 0.f : dalpha * e.G;
-                a[CH + 1] = dq * e.dx * e.dx;
-                a[CH + 2] = 2.f * dq * e.dx * e.dy;
-                a[CH + 3] = dq * e.dy * e.dy;
-                a[CH + 4] = -2.f * dq * (s0.z * e.dx + s0.w * e.dy);
-                a[CH + 5] = -2.f * dq * (s0.w * e.dx + s1.x * e.dy);
-            } else {
-#pragma unroll
-                for (int c = 0; c < CS; ++c) a[c] = w * gch[4 + c];
-            }
-            S += w * s;
-            T = Tk;
-        } else {
-#pragma unroll
-            for (int c = 0; c < V; ++c) a[c] = 0.f;
-        }
-        reduce_scatter<V>(a, lane);
-        if (my_own) {
-            const float v = a[0];
-            const int id = my_id;
-            float* dst = nullptr;
-            if (GEO) {
-                if (id < 3) dst = d_colors + 3 * (size_t)gid + id;
-                else if (id == 3) dst = geo + (size_t)gid * GW_STRIDE + GW_DEPTH;
-                else if (id < CH) dst = (id - 4 < csem) ? d_features + (size_t)gid * fstride + (id - 4) : nullptr;
-                else if (id == CH) dst = d_opacity + gid;
-                else if (id == CH + 1) dst = geo + (size_t)gid * GW_STRIDE + GW_A;
-                else if (id == CH + 2) dst = geo + (size_t)gid * GW_STRIDE + GW_B;
-                else if (id == CH + 3) dst = geo + (size_t)gid * GW_STRIDE + GW_C;
-                else if (id == CH + 4) dst = geo + (size_t)gid * GW_STRIDE + GW_MX;
-                else dst = geo + (size_t)gid * GW_STRIDE + GW_MY;
-            } else {
-                dst = (id < csem) ? d_features + (size_t)gid * fstride + id : nullptr;
-            }
-            if (dst) unsafeAtomicAdd(dst, v);
-        }
-    }
-}
-
-// Matrix-core form.  The walk runs back to front 16 Gaussians at a time.  List
+// The walk runs back to front, 16 Gaussians at a time.  List
 // entries and splat records are fetched two batches ahead and the batch's
 // channel rows one batch ahead (vector loads into registers, then LDS), so
 // the per-Gaussian work reads only LDS.  Per Gaussian each pixel recovers
@@ -522,14 +415,9 @@ template <int CS, bool GEO, bool EXACT = true>
 static void launch_bwd(const xgs_gaussians* g, const xgs_projected* p, const xgs_binning* b,
                        const TileGrid& tg, const float* d_out, const float* final_T,
                        const int32_t* n_last, xgs_gaussians_grad* gr, float* geo, hipStream_t st) {
-    if (render_variant() == 1)
-        hipLaunchKernelGGL((render_bwd_kernel<CS, GEO, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
-                           b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
-                           g->c_sem, tg, d_out, final_T, n_last, gr->colors, gr->features, gr->opacity, geo);
-    else
-        hipLaunchKernelGGL((render_bwd_mfma_kernel<CS, GEO, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st,
-                           b->ranges, b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
-                           g->c_sem, tg, d_out, final_T, n_last, gr->colors, gr->features, gr->opacity, geo);
+    hipLaunchKernelGGL((render_bwd_mfma_kernel<CS, GEO, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
+                       b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features, g->c_sem, tg,
+                       d_out, final_T, n_last, gr->colors, gr->features, gr->opacity, geo);
 }
 
 template <bool GEO>

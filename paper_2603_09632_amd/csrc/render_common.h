@@ -73,8 +73,4 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-// Compositing kernel generation: 2 = matrix-core channel sums (default),
-// 1 = per-pair VALU channel sums (kept for comparison; XGS_RENDER_VARIANT=1).
-int render_variant();
-
 }  // namespace xgs

@@ -9,63 +9,8 @@ namespace xgs {
 // CS: compile-time semantic channel count.  EXACT: csem == CS, so feature
 // rows have a compile-time stride and merge into wide scalar loads; otherwise
 // CS only bounds csem and channels >= csem are neither read nor written.
-template <int CS, bool EXACT>
-__global__ void __launch_bounds__(64) render_fwd_kernel(
-    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
-    const float4* __restrict__ splat, const float* __restrict__ colors,
-    const float* __restrict__ features, int csem, TileGrid g, float* __restrict__ out,
-    float* __restrict__ final_T, int32_t* __restrict__ n_last) {
-    const QuadPix P = quad_pixel(g);
-    if (P.tile >= g.tiles) return;
-    constexpr int CH = 4 + CS;
-    float acc[CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) acc[c] = 0.f;
-    float T = 1.f;
-    uint32_t last = 0;
-    bool done = !P.inside;
-    const uint32_t start = uniform(ranges[2 * P.tile]);
-    const uint32_t end = uniform(ranges[2 * P.tile + 1]);
-    for (uint32_t j = start; j < end; ++j) {
-        if (__ballot(!done) == 0ull) break;
-        const uint32_t gid = uniform(vals[j]);
-        const float4 s0 = splat[2 * gid];
-        const float4 s1 = splat[2 * gid + 1];
-        const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
-        bool contrib = !done && e.alpha >= kAlphaMin;
-        if (__ballot(contrib) == 0ull) continue;
-        const float Tn = T * (1.f - e.alpha);
-        if (contrib && Tn < kTStop) {
-            done = true;
-            contrib = false;
-        }
-        if (contrib) {
-            const float w = e.alpha * T;
-            const float* col = colors + 3 * (size_t)gid;
-            acc[0] += w * col[0];
-            acc[1] += w * col[1];
-            acc[2] += w * col[2];
-            acc[3] += w * s1.z;
-            const float* f = features + (size_t)gid * (EXACT ? CS : csem);
-#pragma unroll
-            for (int c = 0; c < CS; ++c)
-                if (EXACT || c < csem) acc[4 + c] += w * f[c];
-            T = Tn;
-            last = j - start + 1;
-        }
-    }
-    if (!P.inside) return;
-    const size_t hw = (size_t)g.hs * g.ws, pix = (size_t)P.m * g.ws + P.n;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) out[c * hw + pix] = acc[c];
-#pragma unroll
-    for (int c = 0; c < CS; ++c)
-        if (EXACT || c < csem) out[(4 + c) * hw + pix] = acc[4 + c];
-    final_T[pix] = T;
-    n_last[pix] = (int32_t)last;
-}
-
-// Matrix-core form.  A wavefront walks its tile list 16 Gaussians at a time.
+//
+// A wavefront takes an 8x8 quadrant of a tile and walks the tile list 16 Gaussians at a time.
 // The list entries and splat records of the next batch are fetched by lanes
 // 0..15 with vector loads while the current batch is walked, so the walk
 // reads only LDS (no dependent global load per Gaussian).  For each Gaussian
@@ -197,12 +142,7 @@ template <int CS, bool EXACT = true>
 static void launch_fwd(const xgs_gaussians* g, const xgs_projected* p, const xgs_binning* b,
                        const TileGrid& tg, float* out, float* final_T, int32_t* n_last,
                        hipStream_t st) {
-    if (render_variant() == 1)
-        hipLaunchKernelGGL((render_fwd_kernel<CS, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
-                           b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
-                           g->c_sem, tg, out, final_T, n_last);
-    else
-        hipLaunchKernelGGL((render_fwd_mfma_kernel<CS, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
+    hipLaunchKernelGGL((render_fwd_mfma_kernel<CS, EXACT>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
                            b->vals, reinterpret_cast<const float4*>(p->splat), g->colors, g->features,
                            g->c_sem, tg, out, final_T, n_last);
 }
