@@ -218,8 +218,8 @@ xgs_status xgs_grid_sample(const float* P, int32_t D, int32_t Hf, int32_t Wf, in
  * XGS_VQ_BF16_RESCORE4: the squared distances of the bf16 roundings x^, e^
  * are formed on MFMA (FP32 accumulation, the norms folded into the product)
  * and each row keeps its 4 best codewords, ranked by half that distance with
- * its lowest 6 + ceil(log2(min(16, ceil(K / 256)))) mantissa bits replaced
- * by the codeword's position (ties to the lower index); the 4 are rescored
+ * its lowest b mantissa bits (6 <= b <= 10, set by K) replaced by the
+ * codeword's position in its sweep (ties to the lower index); the 4 are rescored
  * with the direct FP32 form and the smallest wins.  E_bf16 [K][D] and
  * e_norm2 [K] must hold xgs_vq_prepare's output for E (xgs_vq_ema_update
  * refreshes them).  BF16 requires D % 8 == 0, K <= 65536, X and E_bf16

@@ -13,6 +13,8 @@
 // Update: rows are grouped by codeword with the stable radix sort, each
 // codeword's rows are summed in ascending row order (bitwise reproducible),
 // and one pass applies the EMA and refreshes the bf16 shadow and its norms.
+#include <algorithm>
+
 #include "sort.h"
 
 namespace xgs {
@@ -155,6 +157,7 @@ constexpr int Q_SLOTS = (Q_BM + Q_BN) * 4;     // slots per chunk buffer
 constexpr int Q_NBUF = 3;
 constexpr int Q_MAX_TILES = 16;                // tiles per part: position fits in 10 bits
 constexpr int Q_MAX_PARTS = 16;                // candidate lists per row in the rescore (x4 <= 64 lanes)
+constexpr int Q_MIN_PARTS = 4;
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
@@ -214,19 +217,29 @@ __device__ __forceinline__ bool cand_before(int ka, int ca, int kb, int cb) {
 }
 
 
-// One wavefront per row; Dp = D rounded up to 32, row stride Dx = Dp + 32.
-__global__ void __launch_bounds__(256) vq_xprep_kernel(const float* __restrict__ X, int64_t N, int D, int Dp,
-                                                      int Dx, uint16_t* __restrict__ Xa) {
+// Both operands are stored chunk-tiled: the 32 columns of chunk kc of a block
+// of rows (128 X rows, or one 256-codeword tile) are contiguous, row after
+// row (64 bytes each), so one direct load of a wavefront reads 1 KB of
+// consecutive memory.  Element (row, col) of a block of B rows sits at
+// ((blk * nkc + col / 32) * B + row % B) * 32 + col % 32, blk = row / B.
+__device__ __forceinline__ size_t tiled_at(int64_t row, int col, int B, int nkc) {
+    return ((size_t)(row / B) * nkc + col / Q_BK) * ((size_t)B * Q_BK) + (size_t)(row % B) * Q_BK + col % Q_BK;
+}
+
+// One wavefront per row of the padded row count Np (rows >= N are zero);
+// Dp = D rounded up to 32, Dx = Dp + 32 columns.
+__global__ void __launch_bounds__(256) vq_xprep_kernel(const float* __restrict__ X, int64_t N, int64_t Np, int D,
+                                                      int Dp, int Dx, uint16_t* __restrict__ Xa) {
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= N) return;
-    const f32x4_t* xr = reinterpret_cast<const f32x4_t*>(X + row * D);
-    uint16_t* orow = Xa + row * Dx;
-    uint2* out = reinterpret_cast<uint2*>(orow);
+    if (row >= Np) return;
+    const int nkc = Dx / Q_BK;
+    const bool real = row < N;
+    const f32x4_t* xr = reinterpret_cast<const f32x4_t*>(X + (real ? row : 0) * D);
     float s = 0.f;
     for (int q = lane; q < Dp / 4; q += 64) {
         uint2 p = make_uint2(0u, 0u);
-        if (q < D / 4) {
+        if (real && q < D / 4) {
             const f32x4_t v = __builtin_nontemporal_load(xr + q);
             uint16_t h[4];
 #pragma unroll
@@ -238,19 +251,19 @@ __global__ void __launch_bounds__(256) vq_xprep_kernel(const float* __restrict__
             p.x = ((uint32_t)h[0] | ((uint32_t)h[1] << 16)) ^ 0x80008000u;  // -x^ (sign flip is exact)
             p.y = ((uint32_t)h[2] | ((uint32_t)h[3] << 16)) ^ 0x80008000u;
         }
-        out[q] = p;
+        *reinterpret_cast<uint2*>(Xa + tiled_at(row, 4 * q, Q_BM, nkc)) = p;
     }
     for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
     if (lane < 8) {
         uint16_t h0, h1, h2;
         split3(0.5f * s, h0, h1, h2);
         uint16_t v[4] = {0, 0, 0, 0};
-        if (lane == 0) { v[0] = kBf16One; v[1] = kBf16One; v[2] = kBf16One; v[3] = h0; }
-        if (lane == 1) { v[0] = h1; v[1] = h2; }
+        if (real && lane == 0) { v[0] = kBf16One; v[1] = kBf16One; v[2] = kBf16One; v[3] = h0; }
+        if (real && lane == 1) { v[0] = h1; v[1] = h2; }
         uint2 p;
         p.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
         p.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
-        out[Dp / 4 + lane] = p;
+        *reinterpret_cast<uint2*>(Xa + tiled_at(row, Dp + 4 * lane, Q_BM, nkc)) = p;
     }
 }
 
@@ -261,10 +274,12 @@ __global__ void __launch_bounds__(256) vq_eprep_kernel(const uint16_t* __restric
     const int lane = threadIdx.x & 63;
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (c >= Kp) return;
+    const int nkc = Dx / Q_BK;
     const bool real = c < K;
-    uint4* out = reinterpret_cast<uint4*>(Ea + (size_t)c * Dx);
     const uint4* in = reinterpret_cast<const uint4*>(Eb + (size_t)(real ? c : 0) * D);
-    for (int q = lane; q < Dp / 8; q += 64) out[q] = (real && q < D / 8) ? in[q] : make_uint4(0u, 0u, 0u, 0u);
+    for (int q = lane; q < Dp / 8; q += 64)
+        *reinterpret_cast<uint4*>(Ea + tiled_at(c, 8 * q, Q_BN, nkc)) =
+            (real && q < D / 8) ? in[q] : make_uint4(0u, 0u, 0u, 0u);
     if (lane < 4) {
         uint16_t g0 = 0x7F80, g1 = 0, g2 = 0;  // +inf: a padded codeword is never chosen
         if (real) split3(0.5f * en[c], g0, g1, g2);
@@ -275,7 +290,7 @@ __global__ void __launch_bounds__(256) vq_eprep_kernel(const uint16_t* __restric
         p.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
         p.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
         p.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
-        out[Dp / 8 + lane] = p;
+        *reinterpret_cast<uint4*>(Ea + tiled_at(c, Dp + 8 * lane, Q_BN, nkc)) = p;
     }
 }
 
@@ -287,9 +302,16 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm = w & 1, wn = w >> 1;
+    // Workgroups go round-robin to the 8 XCDs.  The parts of one row block
+    // take the same XCD (and neighbouring dispatch slots), so its X chunks
+    // are fetched into one L2 and served to all of them.
     const int64_t blk = blockIdx.x;
-    const int p = (int)(blk % parts);
-    const int64_t r0 = (blk / parts) * Q_BM;
+    const int64_t grp = blk / (8 * parts);
+    const int within = (int)(blk - grp * 8 * parts);
+    const int p = within >> 3;
+    const int64_t rb = grp * 8 + (within & 7);
+    const int64_t r0 = rb * Q_BM;
+    if (r0 >= N) return;  // padding of the last group (whole workgroup)
     const int c_part = p * tiles_part * Q_BN;
     const int tiles = min(tiles_part, (K - c_part + Q_BN - 1) / Q_BN);
     const int nkc = Dx / Q_BK;
@@ -299,22 +321,22 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
     // This wave's direct loads: instruction m fills slots 64 j .. 64 j + 63
     // of a buffer, j = w + 4 m: X rows 16 j + lane / 4 for m = 0, 1, codeword
     // rows 16 (w + 4 (m - 2)) + lane / 4 for m = 2..5; lane & 3 is the slot
-    // within the row, holding segment (lane & 3) ^ q_swz(row).  Per-lane byte
-    // offsets are fixed; the chunk moves the (scalar) bases.
+    // within the row, holding segment (lane & 3) ^ q_swz(row).  In the
+    // chunk-tiled operands those 16 rows are 1 KB of consecutive memory; the
+    // per-lane byte offsets are fixed and the chunk moves the (scalar) bases.
     const int lr = lane >> 2;
-    const char* xbase = reinterpret_cast<const char*>(Xa + r0 * Dx);
+    const char* xbase = reinterpret_cast<const char*>(Xa + (size_t)rb * nkc * Q_BM * Q_BK);
     const char* ebase = reinterpret_cast<const char*>(Ea + (size_t)c_part * Dx);
     uint32_t xoff[2], eoff[4];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const int row = 16 * (w + 4 * m) + lr;
-        const int rc = row < rows_here ? row : rows_here - 1;
-        xoff[m] = (uint32_t)rc * (uint32_t)(2 * Dx) + 16u * (uint32_t)((lane & 3) ^ q_swz(row));
+        xoff[m] = (uint32_t)row * 64u + 16u * (uint32_t)((lane & 3) ^ q_swz(row));
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int row = 16 * (w + 4 * m) + lr;
-        eoff[m] = (uint32_t)row * (uint32_t)(2 * Dx) + 16u * (uint32_t)((lane & 3) ^ q_swz(row));
+        eoff[m] = (uint32_t)row * 64u + 16u * (uint32_t)((lane & 3) ^ q_swz(row));
     }
     // next chunk to issue: tile, chunk within the tile, buffer
     int n_tl = 0, n_kc = 0, n_b = 0;
@@ -323,8 +345,8 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
         uint4* dst = qbuf + n_b * Q_SLOTS;
         if (++n_kc == nkc) { n_kc = 0; ++n_tl; }
         n_b = n_b == Q_NBUF - 1 ? 0 : n_b + 1;
-        const char* xb = xbase + kc * 64;
-        const char* eb = ebase + ((size_t)tl * Q_BN * Dx + (size_t)kc * Q_BK) * 2;
+        const char* xb = xbase + (size_t)kc * (Q_BM * Q_BK * 2);
+        const char* eb = ebase + ((size_t)tl * nkc + kc) * (Q_BN * Q_BK * 2);
 #pragma unroll
         for (int m = 0; m < 2; ++m)
             __builtin_amdgcn_global_load_lds((glb_void_t*)(xb + xoff[m]), (lds_void_t*)(dst + 64 * (w + 4 * m)), 16,
@@ -555,7 +577,10 @@ struct VqPlan {
 static VqPlan vq_plan(int K) {
     VqPlan p;
     p.tiles = (K + Q_BN - 1) / Q_BN;
-    p.parts = (p.tiles + Q_MAX_TILES - 1) / Q_MAX_TILES;
+    // At least Q_MIN_PARTS parts when there are enough tiles: the parts of a
+    // row block share its X chunks in one L2 (the sweep reads them once per
+    // tile).
+    p.parts = std::max((p.tiles + Q_MAX_TILES - 1) / Q_MAX_TILES, std::min(Q_MIN_PARTS, p.tiles));
     p.tiles_part = (p.tiles + p.parts - 1) / p.parts;
     p.parts = (p.tiles + p.tiles_part - 1) / p.tiles_part;
     int b = 0;
@@ -565,13 +590,14 @@ static VqPlan vq_plan(int K) {
 }
 
 static int vq_dp(int D) { return (D + Q_BK - 1) / Q_BK * Q_BK; }
+static int64_t vq_np(int64_t N) { return (N + Q_BM - 1) / Q_BM * Q_BM; }
 
 static VqWs carve_vq(void* base, int64_t N, int D, const VqPlan& plan, size_t* bytes) {
     Carve c(base);
     VqWs w;
     const int64_t n1 = N > 0 ? N : 1;
     const size_t dx = (size_t)vq_dp(D) + Q_BK;
-    w.xa = c.take<uint16_t>((size_t)n1 * dx);
+    w.xa = c.take<uint16_t>((size_t)vq_np(n1) * dx);
     w.ea = c.take<uint16_t>((size_t)plan.parts * plan.tiles_part * Q_BN * dx);
     w.cand = c.take<int2>((size_t)n1 * plan.parts * 4);
     *bytes = c.total();
@@ -762,7 +788,7 @@ static xgs_status vq_bf16_setup(const char* who, int64_t N, int32_t D, int32_t K
     const int64_t dx = vq_dp(D) + Q_BK;
     if ((int64_t)plan->parts * plan->tiles_part * Q_BN * dx >= ((int64_t)1 << 31) || Q_BM * dx >= ((int64_t)1 << 30))
         return fail(XGS_ERR_UNSUPPORTED, std::string(who) + ": codebook above 2^31 bf16 elements");
-    if ((N + Q_BM - 1) / Q_BM * plan->parts >= ((int64_t)1 << 31))
+    if (((N + Q_BM - 1) / Q_BM + 7) / 8 * 8 * plan->parts >= ((int64_t)1 << 31))
         return fail(XGS_ERR_UNSUPPORTED, std::string(who) + ": N too large");
     if (!aligned(ws, 256)) return fail(XGS_ERR_INVALID_ARG, std::string(who) + ": workspace must be 256-byte aligned");
     size_t need = 0;
@@ -785,7 +811,8 @@ extern "C" xgs_status xgs_vq_stage(const float* X, int64_t N, int32_t D, const u
     const int Dp = vq_dp(D), Dx = Dp + Q_BK;
     const int Kp = plan.parts * plan.tiles_part * Q_BN;
     if (N > 0)
-        hipLaunchKernelGGL(vq_xprep_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, X, N, D, Dp, Dx, w.xa);
+        hipLaunchKernelGGL(vq_xprep_kernel, dim3((unsigned)((vq_np(N) + 3) / 4)), dim3(256), 0, st, X, N, vq_np(N), D, Dp,
+                           Dx, w.xa);
     hipLaunchKernelGGL(vq_eprep_kernel, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, st, E_bf16, e_norm2, K, D, Kp,
                        Dp, Dx, w.ea);
     return check_launch("xgs_vq_stage");
@@ -798,7 +825,7 @@ extern "C" xgs_status xgs_vq_candidates(int64_t N, int32_t D, int32_t K, void* w
     VqWs w;
     if (xgs_status s = vq_bf16_setup("xgs_vq_candidates", N, D, K, ws, ws_bytes, &plan, &w)) return s;
     if (N == 0) return XGS_OK;
-    const int64_t blocks = (N + Q_BM - 1) / Q_BM * plan.parts;
+    const int64_t blocks = ((N + Q_BM - 1) / Q_BM + 7) / 8 * 8 * plan.parts;
     hipLaunchKernelGGL(vq_gemm_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, w.xa, N,
                        vq_dp(D) + Q_BK, w.ea, K, plan.parts, plan.tiles_part, plan.seq_bits, w.cand);
     return check_launch("xgs_vq_candidates");

@@ -69,7 +69,7 @@ class _Request:
 class _BufferSet:
     """Scratch for one in-flight request of a (scene, resolution) pair."""
 
-    def __init__(self, server: "Server", scene: str, res: Resolution):
+    def __init__(self, server: "Server", scene: str, res: Resolution, cap: int):
         g = server.scenes[scene]
         dev = server.device
         self.key = (scene, res)
@@ -78,7 +78,7 @@ class _BufferSet:
         self.viewmat_host = torch.empty((4, 4), dtype=torch.float32).pin_memory()
         self.viewmat_dev = torch.zeros((4, 4), dtype=torch.float32, device=dev)
         self.proj = Projected.alloc(g.n, dev)
-        self.cap = server.capacity(scene, res)
+        self.cap = cap
         self.binning: Binning = alloc_binning(g.n, self.cap, self.cam, dev)
         self.out = torch.empty((4 + g.c_sem, hs, ws), device=dev)
         self.final_T = torch.empty((hs, ws), device=dev)
@@ -132,14 +132,32 @@ class Server:
 
     # ------------------------------------------------------------ capacity
     def capacity(self, scene: str, res: Resolution) -> int:
-        """Instance capacity of a buffer set: the larger of a generous bound
-        (3 instances per Gaussian) and the tile count; an overflow is detected
-        and the request re-rendered eagerly at the exact size."""
+        """Instance capacity of a new buffer set.  Until a (scene, resolution)
+        pair has been measured this is a generous bound (4 instances per
+        Gaussian, at least the tile count), used for admission; the first
+        buffer set of a pair measures the instance count at its request's pose
+        and keeps 1.5x of it.  A later overflow is detected on the device, the
+        request is re-rendered eagerly at the exact size, the capacity grows
+        to 1.25x of what was needed and the undersized set is discarded."""
+        key = (scene, res)
+        if key in self._capacity:
+            return self._capacity[key]
+        n = self.scenes[scene].n
+        _, _, ty, tx = grid_dims(camera(res.width, res.height, res.fx, res.fy, res.cx, res.cy))
+        return max(4 * n, ty * tx) + 1024
+
+    def _measure_capacity(self, scene: str, res: Resolution, viewmat: np.ndarray) -> int:
         key = (scene, res)
         if key not in self._capacity:
-            n = self.scenes[scene].n
-            _, _, ty, tx = grid_dims(camera(res.width, res.height, res.fx, res.fy, res.cx, res.cy))
-            self._capacity[key] = max(3 * n, ty * tx) + 1024
+            g = self.scenes[scene]
+            cam = camera(res.width, res.height, res.fx, res.fy, res.cx, res.cy, near=self.near)
+            s = self.streams[0]
+            with torch.cuda.stream(s):
+                vm = torch.from_numpy(viewmat).to(self.device, non_blocking=False)
+                p = xgs_project_posed(g, cam, vm)
+                m = int(p.tiles_touched.to(torch.int64).sum().item())
+            _, _, ty, tx = grid_dims(cam)
+            self._capacity[key] = max(int(1.5 * m), ty * tx) + 1024
         return self._capacity[key]
 
     # ----------------------------------------------------------------- api
@@ -169,7 +187,7 @@ class Server:
                 "peak_hbm_scratch_MB": self.peak_ledger_bytes / 2 ** 20, "budget_MB": self.budget / 2 ** 20}
 
     # ------------------------------------------------------------ internals
-    def _acquire(self, scene: str, res: Resolution) -> Optional[_BufferSet]:
+    def _acquire(self, scene: str, res: Resolution, viewmat: np.ndarray) -> Optional[_BufferSet]:
         key = (scene, res)
         if self._pool[key]:
             bs = self._pool[key].pop()
@@ -183,7 +201,7 @@ class Server:
             del victim
         if self.ledger_bytes + need > self.budget:
             return None
-        bs = _BufferSet(self, scene, res)
+        bs = _BufferSet(self, scene, res, self._measure_capacity(scene, res, viewmat))
         self.ledger_bytes += bs.nbytes
         self.peak_ledger_bytes = max(self.peak_ledger_bytes, self.ledger_bytes)
         return bs
@@ -238,13 +256,17 @@ class Server:
                 b = alloc_binning(g.n, m, bs.cam, self.device)
                 xgs_tile_sort(p, bs.cam, g.n, b)
                 image, final_T, _ = xgs_render_fwd(g, p, b, bs.cam)
-                self._capacity[bs.key] = int(m * 1.25) + 1024
+                self._capacity[bs.key] = max(self._capacity.get(bs.key, 0), int(m * 1.25) + 1024)
                 self.overflows += 1
             s.synchronize()
+            # the set is too small for this pair: drop it instead of pooling it
+            self.ledger_bytes -= bs.nbytes
+            bs = None
         t = time.perf_counter()
         res = RenderResult(image, final_T, t - req.t_arrival, t_launch - req.t_arrival)
         self.completed.append(res)
-        self._release(bs)
+        if bs is not None:
+            self._release(bs)
         req.future.set_result(res)
 
     def _loop(self):
@@ -257,7 +279,7 @@ class Server:
             # admit in arrival order while slots and memory allow
             while self._pending and len(self._inflight) < self.max_inflight:
                 req = self._pending[0]
-                bs = self._acquire(req.scene, req.res)
+                bs = self._acquire(req.scene, req.res, req.viewmat)
                 if bs is None:
                     if not self._inflight:  # cannot fit even on an idle GPU
                         self._pending.popleft()

@@ -104,5 +104,11 @@ def test_capacity_overflow_is_recovered(xgs, world):
     srv._capacity[(sc, r)] = 1000  # far too small: the graph's sort overflows
     img = np_(srv.render_now(sc, vm, r).image)
     assert srv.overflows == 1
+    # the undersized set was dropped: the next request gets a set that fits
+    img2 = np_(srv.render_now(sc, vm, r).image)
+    assert srv.overflows == 1
+    assert srv.ledger_bytes > 0
     srv.close()
-    np.testing.assert_array_equal(img, np_(direct(xgs, scenes[sc], vm, r)))
+    ref = np_(direct(xgs, scenes[sc], vm, r))
+    np.testing.assert_array_equal(img, ref)
+    np.testing.assert_array_equal(img2, ref)
