@@ -375,3 +375,84 @@ def ema_update(X, idx, N_ema, M_ema, decay: float, eps: float, mode: int = LAPLA
         nt = (N_new + eps) / (tot + K * eps) * tot
         E_new = M_new / nt[:, None]
     return N_new, M_new, E_new, counts, sums
+
+
+# ------------------------------------------------------------ semantic phase
+# Sec. 3.2.2 (online VQ module): each Gaussian carries logits z_i over the L
+# codewords, w_i = softmax(z_i), decoded feature E^T w_i; App. E renders the
+# mixture weights and decodes per pixel, F(x) = E^T w(x).  App. D (masked loss
+# evaluation): L_grid = lambda_sem [L_cos + L_1] over the valid grid pixels,
+# geometry frozen (Sec. 3.2.2, parallelized pipeline).
+#
+# Readings (the paper does not spell these out):
+#   L_cos = (1/n) sum_{x valid} (1 - cos(G^(x), G*(x))),
+#           cos(a, b) = <a, b> / max(|a| |b|, 1e-8);
+#   L_1   = (1/(n D)) sum_{x valid} sum_d |G^_d(x) - G*_d(x)|;
+#   n = number of valid pixels; n = 0 gives L = 0 and zero gradients;
+#   d|t|/dt = sign(t) with sign(0) = 0.
+COS_EPS = 1e-8
+
+
+def semantic_softmax(z):
+    """w_i = softmax(z_i) over the codewords (rows of z)."""
+    z = _f64(z)
+    e = np.exp(z - z.max(axis=1, keepdims=True))
+    return e / e.sum(axis=1, keepdims=True)
+
+
+def semantic_softmax_bwd(w, dw):
+    """dL/dz_i = w_i * (dL/dw_i - <dL/dw_i, w_i>)."""
+    w = _f64(w)
+    dw = _f64(dw)
+    return w * (dw - (dw * w).sum(axis=1, keepdims=True))
+
+
+def semantic_loss(wmap, E, Gstar, V, lam: float = 1.0):
+    """Masked cosine + L1 loss of the decoded map against the targets.
+
+    wmap [L][Hs][Ws] rendered mixture weights, E [L][D] codebook,
+    Gstar [D][Hs][Ws] targets, V [Hs][Ws] validity.  Returns (loss,
+    dL/dwmap [L][Hs][Ws]) in FP64."""
+    wmap = _f64(wmap)
+    E = _f64(E)
+    Gs = _f64(Gstar)
+    L, Hs, Ws = wmap.shape
+    D = E.shape[1]
+    valid = np.asarray(V).astype(bool)
+    n = int(valid.sum())
+    dw = np.zeros_like(wmap)
+    if n == 0:
+        return 0.0, dw
+    W = wmap.reshape(L, -1)[:, valid.ravel()]          # [L][n]
+    B = Gs.reshape(D, -1)[:, valid.ravel()]            # [D][n]
+    A = E.T @ W                                         # decoded G^ [D][n]
+    na = np.sqrt((A * A).sum(0))
+    nb = np.sqrt((B * B).sum(0))
+    dot = (A * B).sum(0)
+    den = np.maximum(na * nb, COS_EPS)
+    cos = dot / den
+    diff = A - B
+    loss_cos = (1.0 - cos).sum() / n
+    loss_l1 = np.abs(diff).sum() / (n * D)
+    # d cos / dA = B / den - [den > eps] cos A / |A|^2
+    scale = np.where(na * nb > COS_EPS, 1.0, 0.0)
+    na2 = np.where(na > 0, na * na, 1.0)
+    dcos = B / den - scale * cos * A / na2
+    g = lam * (-dcos / n + np.sign(diff) / (n * D))    # dL/dA [D][n]
+    dwv = E @ g                                         # dL/dW [L][n]
+    dw.reshape(L, -1)[:, valid.ravel()] = dwv
+    return lam * (loss_cos + loss_l1), dw
+
+
+def semantic_phase(scene, cam, z, E, Gstar, V, lam: float = 1.0, tile_mask=None):
+    """One semantic-phase evaluation: w = softmax(z) rendered as the feature
+    channels, decoded, masked loss, and dL/dz through the feature-only
+    backward.  Returns (loss, dL/dz [N][L], rendered wmap [L][Hs][Ws])."""
+    w = semantic_softmax(z)
+    sc = scene.__class__(**{**scene.__dict__, "features": w})
+    r = render(sc, cam, tile_mask)
+    wmap = r.out[4:]
+    val, dwmap = semantic_loss(wmap, E, Gstar, V, lam)
+    g = np.concatenate([np.zeros((4,) + wmap.shape[1:]), dwmap], axis=0)
+    gr = render_grad(sc, cam, g, r, tile_mask=tile_mask)
+    return val, semantic_softmax_bwd(w, gr.features), wmap
