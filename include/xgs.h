@@ -212,6 +212,31 @@ xgs_status xgs_grid_sample(const float* P, int32_t D, int32_t Hf, int32_t Wf, in
                            int32_t W, int32_t stride, int32_t off_y, int32_t off_x, int32_t mode,
                            float* G, uint8_t* V, xgs_stream_t stream);
 
+/* ------------------------------------------- f1: semantic phase (Sec. 3.2.2, App. D, App. E)
+ * Mixture weights w_i = softmax(z_i) over L codewords (Sec. 3.2.2); z, w,
+ * dL/dw, dL/dz are [N][L] row-major FP32, 16-byte aligned; L in
+ * {4, 8, 16, 32, 64}.  xgs_semantic_softmax_bwd: dL/dz = w (dL/dw - <dL/dw, w>). */
+xgs_status xgs_semantic_softmax(const float* z, int64_t N, int32_t L, float* w, xgs_stream_t stream);
+xgs_status xgs_semantic_softmax_bwd(const float* w, const float* dw, int64_t N, int32_t L, float* dz,
+                                    xgs_stream_t stream);
+
+/* Decode and masked grid loss (App. D Eq. (loss), App. E F(x) = E^T w(x)):
+ * wmap [4+L][Hs][Ws] is xgs_render_fwd's output with the mixture weights as
+ * the semantic channels (channels 0..3 are not read); E [L][D] codebook
+ * (D % 4 == 0, L D + 65 (L + 17) floats must fit 160 KB of LDS);
+ * Gstar [D][Hs][Ws] targets; V [Hs][Ws] validity (NULL: all valid).
+ *   loss = lambda [ (1/n) sum_valid (1 - cos(G^, G*)) + (1/(n D)) sum_valid |G^ - G*|_1 ],
+ *   G^(x) = E^T w(x), cos(a, b) = <a, b> / max(|a| |b|, 1e-8), n = #valid
+ *   (n = 0: loss 0, zero gradient).
+ * Writes *loss (device float) and d_out [4+L][Hs][Ws] = dL/dwmap with the
+ * colour and depth channels zero, ready for xgs_render_bwd with
+ * XGS_BWD_FEATURES_ONLY.  Deterministic (fixed reduction order).  ws:
+ * xgs_semantic_loss_workspace(Hs, Ws) bytes, 256-byte aligned. */
+size_t xgs_semantic_loss_workspace(int32_t Hs, int32_t Ws);
+xgs_status xgs_semantic_loss(const float* wmap, int32_t L, int32_t Hs, int32_t Ws, const float* E, int32_t D,
+                             const float* Gstar, const uint8_t* V, float lambda, float* d_out, float* loss,
+                             void* ws, size_t ws_bytes, xgs_stream_t stream);
+
 /* ------------------------------------------------------ a6: VQ assignment
  * a_n = argmin_l ||x_n - E_l||^2 (Sec. 3.2.2), ties to the lowest l.
  * XGS_VQ_FP32: direct FP32 sum of (x - e)^2 over every codeword.

@@ -34,7 +34,8 @@ __all__ = [
     "XgsError", "Gaussians", "Projected", "Binning", "camera", "camera_from", "grid_dims",
     "xgs_project", "xgs_project_posed", "alloc_binning", "xgs_tile_sort", "xgs_render_fwd", "xgs_render_bwd",
     "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_stage", "xgs_vq_candidates", "xgs_vq_rescore",
-    "vq_assign_workspace", "xgs_vq_ema_update", "render",
+    "vq_assign_workspace", "xgs_vq_ema_update", "xgs_semantic_softmax", "xgs_semantic_softmax_bwd",
+    "xgs_semantic_loss", "semantic_step", "render",
 ]
 
 
@@ -282,6 +283,55 @@ def xgs_vq_rescore(X: torch.Tensor, E: torch.Tensor, workspace: torch.Tensor, id
     check(lib.xgs_vq_rescore(_ptr(X), N, D, _ptr(E), K, _ptr(idx), _ptr(dist), _ptr(workspace), workspace.numel(),
                              _stream(stream)), "xgs_vq_rescore")
     return idx, dist
+
+
+def xgs_semantic_softmax(z: torch.Tensor, w=None, stream=None) -> torch.Tensor:
+    N, L = z.shape
+    w = w if w is not None else torch.empty_like(z)
+    check(lib.xgs_semantic_softmax(_ptr(z), N, L, _ptr(w), _stream(stream)), "xgs_semantic_softmax")
+    return w
+
+
+def xgs_semantic_softmax_bwd(w: torch.Tensor, dw: torch.Tensor, dz=None, stream=None) -> torch.Tensor:
+    N, L = w.shape
+    dz = dz if dz is not None else torch.empty_like(w)
+    check(lib.xgs_semantic_softmax_bwd(_ptr(w), _ptr(dw), N, L, _ptr(dz), _stream(stream)),
+          "xgs_semantic_softmax_bwd")
+    return dz
+
+
+def xgs_semantic_loss(wmap: torch.Tensor, E: torch.Tensor, Gstar: torch.Tensor, V=None, lam: float = 1.0,
+                      d_out=None, loss=None, workspace=None, stream=None):
+    """Masked cosine + L1 grid loss of the decoded map E^T w(x) (wmap is the
+    [4+L][Hs][Ws] render); returns (loss [1] device tensor, d_out)."""
+    C, Hs, Ws = wmap.shape
+    L, D = E.shape
+    assert C == 4 + L and Gstar.shape == (D, Hs, Ws)
+    d_out = d_out if d_out is not None else torch.empty_like(wmap)
+    loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=wmap.device)
+    if workspace is None:
+        workspace = torch.empty(int(lib.xgs_semantic_loss_workspace(Hs, Ws)), dtype=torch.uint8,
+                                device=wmap.device)
+    check(lib.xgs_semantic_loss(_ptr(wmap), L, Hs, Ws, _ptr(E), D, _ptr(Gstar), _ptr(V), float(lam), _ptr(d_out),
+                                _ptr(loss), _ptr(workspace), workspace.numel(), _stream(stream)),
+          "xgs_semantic_loss")
+    return loss, d_out
+
+
+def semantic_step(g: "Gaussians", p: "Projected", b: "Binning", cam, z: torch.Tensor, E: torch.Tensor,
+                  Gstar: torch.Tensor, V=None, lam: float = 1.0, stream=None):
+    """One semantic-phase evaluation with the geometry frozen (Sec. 3.2.2):
+    w = softmax(z) rendered as the semantic channels over the given binning,
+    decoded, masked loss against Gstar, and dL/dz through the feature-only
+    backward.  ``g`` supplies the frozen geometry and colours; its features are
+    replaced by w.  Returns (loss [1], dL/dz [N][L], rendered map)."""
+    w = xgs_semantic_softmax(z, stream=stream)
+    gw = Gaussians(g.means, g.log_scales, g.quats, g.opacity, g.colors, w)
+    out, fT, nl = xgs_render_fwd(gw, p, b, cam, stream=stream)
+    loss, d_out = xgs_semantic_loss(out, E, Gstar, V, lam, stream=stream)
+    grads = xgs_render_bwd(gw, p, b, cam, d_out, fT, nl, flags=BWD_FEATURES_ONLY, stream=stream)
+    dz = xgs_semantic_softmax_bwd(w, grads.features, stream=stream)
+    return loss, dz, out
 
 
 def xgs_vq_ema_update(X, idx, N_ema, M_ema, E, E_bf16=None, e_norm2=None, decay: float = 0.99,
