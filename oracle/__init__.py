@@ -54,7 +54,7 @@ def lib():
             build()
         _lib = ctypes.CDLL(_LIB)
         for name in ("orc_project", "orc_composite_fwd", "orc_composite_list", "orc_composite_bwd", "orc_composite_tiles",
-                     "orc_project_bwd", "orc_vq_assign", "orc_grid_info"):
+                     "orc_project_bwd", "orc_pose_grad", "orc_vq_assign", "orc_grid_info"):
             getattr(_lib, name).restype = ctypes.c_int
         _lib.orc_bin.restype = ctypes.c_int64
     return _lib
@@ -456,3 +456,76 @@ def semantic_phase(scene, cam, z, E, Gstar, V, lam: float = 1.0, tile_mask=None)
     g = np.concatenate([np.zeros((4,) + wmap.shape[1:]), dwmap], axis=0)
     gr = render_grad(sc, cam, g, r, tile_mask=tile_mask)
     return val, semantic_softmax_bwd(w, gr.features), wmap
+
+
+# ----------------------------------------------------------------- tracking
+# Eq. (tracking) / Eq. (loss_track): the pose is refined against the colour
+# image and the depth map with the map frozen.
+# Readings: L_photo = (1/(3 P)) sum_x sum_{c<3} |I^_c(x) - I_c(x)| over the P
+# grid pixels; the depth term is lambda_d (1/P_D) sum_{x: D(x) > 0}
+# |D^(x) - D(x)| over the P_D pixels with a depth value (0 when there are
+# none); d|t|/dt = sign(t), sign(0) = 0.
+
+
+def track_loss(out, image, depth, lam_d: float):
+    """Returns (L_track, dL/dout) with dL/dout shaped like out [C][Hs][Ws]
+    (zero on the semantic channels)."""
+    out = _f64(out)
+    I = _f64(image)
+    P = out.shape[1] * out.shape[2]
+    d = np.zeros_like(out)
+    diff = out[:3] - I
+    val = np.abs(diff).sum() / (3 * P)
+    d[:3] = np.sign(diff) / (3 * P)
+    if depth is not None and lam_d != 0.0:
+        Dm = _f64(depth)
+        has = Dm > 0
+        nd = int(has.sum())
+        if nd:
+            dd = out[3] - Dm
+            val += lam_d * np.abs(dd[has]).sum() / nd
+            d[3][has] = lam_d * np.sign(dd[has]) / nd
+    return float(val), d
+
+
+def pose_grad(scene, cam, g, r: Render | None = None, tile_mask=None):
+    """dL/dxi (6 values: translation, rotation) of L = sum g * out for the
+    left perturbation T(xi) = exp(xi^) T of the world-to-camera pose."""
+    if r is None:
+        r = render(scene, cam, tile_mask)
+    n = scene.n
+    C = r.chan.shape[1]
+    d_m2 = np.zeros((n, 2)); d_co = np.zeros((n, 3)); d_op = np.zeros(n); d_ch = np.zeros((n, C))
+    tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, dtype=np.uint8)
+    lib().orc_composite_bwd(ctypes.c_int64(n), _p(_f64(r.proj.mean2d)), _p(_f64(r.proj.conic)),
+                            _p(_f64(scene.opacity)), _p(r.chan), ctypes.c_int32(C),
+                            _p(np.ascontiguousarray(r.order, np.uint32)),
+                            _p(np.ascontiguousarray(r.ranges, np.uint32)), _p(cam_array(cam)),
+                            _p(_f64(g)), _p(tm), _p(d_m2), _p(d_co), _p(d_op), _p(d_ch))
+    d_pose = np.zeros(6)
+    lib().orc_pose_grad(ctypes.c_int64(n), _p(_f64(scene.means)), _p(_f64(scene.log_scales)),
+                        _p(_f64(scene.quats)), _p(_f64(scene.opacity)), _p(cam_array(cam)), _p(d_m2), _p(d_co),
+                        _p(np.ascontiguousarray(d_ch[:, 3])), _p(d_pose))
+    return d_pose
+
+
+def se3_exp(xi):
+    """exp(xi^) for xi = (rho, phi) as a 4x4 matrix (Rodrigues; the
+    translation part uses the left Jacobian V)."""
+    rho = np.asarray(xi[:3], np.float64)
+    phi = np.asarray(xi[3:], np.float64)
+    th = float(np.linalg.norm(phi))
+    K = np.array([[0, -phi[2], phi[1]], [phi[2], 0, -phi[0]], [-phi[1], phi[0], 0]])
+    if th < 1e-12:
+        R = np.eye(3) + K
+        V = np.eye(3) + 0.5 * K
+    else:
+        a = np.sin(th) / th
+        b = (1 - np.cos(th)) / th ** 2
+        c = (th - np.sin(th)) / th ** 3
+        R = np.eye(3) + a * K + b * K @ K
+        V = np.eye(3) + b * K + c * K @ K
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = V @ rho
+    return T

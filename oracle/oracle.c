@@ -481,6 +481,54 @@ int orc_composite_bwd(int64_t n, const double* mean2d, const double* conic, cons
  * mean2d = f p_xy / p_z + c, depth = p_z.  The clamp of x/z, y/z in J is
  * differentiated as the piecewise function it is.  Culled Gaussians get 0.
  */
+/* Adjoint of one Gaussian's projection down to the camera frame: from
+ * dL/dmean2d, dL/dconic and dL/ddepth to dL/dp (camera-space mean, through
+ * mean2d, J and the depth channel; clamped guard components pass nothing) and
+ * dL/dSigma_cam (symmetric). */
+static void adjoint_cam(const cam_t* k, const proj_t* P, const double* gcon, double gmx, double gmy,
+                        double gdepth, double dp[3], double dSc[3][3]) {
+    double z = P->p[2];
+    /* conic -> Sigma' : dS = -K Ghat K with Ghat = [[gA, gB/2],[gB/2, gC]] */
+    double K[2][2] = {{P->conic[0], P->conic[1]}, {P->conic[1], P->conic[2]}};
+    double Gh[2][2] = {{gcon[0], 0.5 * gcon[1]}, {0.5 * gcon[1], gcon[2]}};
+    double KG[2][2], dS[2][2];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) KG[r][c] = K[r][0] * Gh[0][c] + K[r][1] * Gh[1][c];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) dS[r][c] = -(KG[r][0] * K[0][c] + KG[r][1] * K[1][c]);
+    /* Sigma' = J Sc J^T (+0.3 I): dSc = J^T dS J ; dJ = 2 dS J Sc */
+    double dJ[2][3], JSc[2][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0;
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) acc += P->J[a][r] * dS[a][b] * P->J[b][c];
+            dSc[r][c] = acc;
+        }
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0;
+            for (int m = 0; m < 3; ++m) acc += P->J[r][m] * P->Sc[m][c];
+            JSc[r][c] = acc;
+        }
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c) dJ[r][c] = 2.0 * (dS[r][0] * JSc[0][c] + dS[r][1] * JSc[1][c]);
+    /* J(p), mean2d(p), depth(p) -> p */
+    dp[0] = dp[1] = dp[2] = 0;
+    double dtx_dpx = P->clx ? 0.0 : 1.0, dtx_dpz = P->clx ? P->tx / z : 0.0;
+    double dty_dpy = P->cly ? 0.0 : 1.0, dty_dpz = P->cly ? P->ty / z : 0.0;
+    dp[2] += dJ[0][0] * (-k->fx / (z * z)) + dJ[1][1] * (-k->fy / (z * z));
+    dp[0] += dJ[0][2] * (-k->fx / (z * z)) * dtx_dpx;
+    dp[2] += dJ[0][2] * (-k->fx / (z * z) * dtx_dpz + 2.0 * k->fx * P->tx / (z * z * z));
+    dp[1] += dJ[1][2] * (-k->fy / (z * z)) * dty_dpy;
+    dp[2] += dJ[1][2] * (-k->fy / (z * z) * dty_dpz + 2.0 * k->fy * P->ty / (z * z * z));
+    dp[0] += gmx * k->fx / z;
+    dp[2] += -gmx * k->fx * P->p[0] / (z * z);
+    dp[1] += gmy * k->fy / z;
+    dp[2] += -gmy * k->fy * P->p[1] / (z * z);
+    dp[2] += gdepth;
+}
+
 int orc_project_bwd(int64_t n, const double* means, const double* log_scales, const double* quats,
                     const double* opac, const double* cam, const double* d_mean2d,
                     const double* d_conic, const double* d_depth, double* d_means,
@@ -492,33 +540,8 @@ int orc_project_bwd(int64_t n, const double* means, const double* log_scales, co
         for (int j = 0; j < 3; ++j) { d_means[3 * i + j] = 0; d_log_scales[3 * i + j] = 0; }
         for (int j = 0; j < 4; ++j) d_quats[4 * i + j] = 0;
         if (P.culled) continue;
-        double z = P.p[2];
-        /* conic -> Sigma' : dS = -K Ghat K with Ghat = [[gA, gB/2],[gB/2, gC]] */
-        double K[2][2] = {{P.conic[0], P.conic[1]}, {P.conic[1], P.conic[2]}};
-        double Gh[2][2] = {{d_conic[3 * i], 0.5 * d_conic[3 * i + 1]},
-                           {0.5 * d_conic[3 * i + 1], d_conic[3 * i + 2]}};
-        double KG[2][2], dS[2][2];
-        for (int r = 0; r < 2; ++r)
-            for (int c = 0; c < 2; ++c) KG[r][c] = K[r][0] * Gh[0][c] + K[r][1] * Gh[1][c];
-        for (int r = 0; r < 2; ++r)
-            for (int c = 0; c < 2; ++c) dS[r][c] = -(KG[r][0] * K[0][c] + KG[r][1] * K[1][c]);
-        /* Sigma' = J Sc J^T (+0.3 I): dSc = J^T dS J ; dJ = 2 dS J Sc */
-        double dSc[3][3], dJ[2][3], JSc[2][3];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) {
-                double acc = 0;
-                for (int a = 0; a < 2; ++a)
-                    for (int b = 0; b < 2; ++b) acc += P.J[a][r] * dS[a][b] * P.J[b][c];
-                dSc[r][c] = acc;
-            }
-        for (int r = 0; r < 2; ++r)
-            for (int c = 0; c < 3; ++c) {
-                double acc = 0;
-                for (int m = 0; m < 3; ++m) acc += P.J[r][m] * P.Sc[m][c];
-                JSc[r][c] = acc;
-            }
-        for (int r = 0; r < 2; ++r)
-            for (int c = 0; c < 3; ++c) dJ[r][c] = 2.0 * (dS[r][0] * JSc[0][c] + dS[r][1] * JSc[1][c]);
+        double dp[3], dSc[3][3];
+        adjoint_cam(&k, &P, d_conic + 3 * i, d_mean2d[2 * i], d_mean2d[2 * i + 1], d_depth[i], dp, dSc);
         /* Sc = Rv Sig Rv^T : dSig = Rv^T dSc Rv */
         double dSig[3][3];
         for (int r = 0; r < 3; ++r)
@@ -554,23 +577,46 @@ int orc_project_bwd(int64_t n, const double* means, const double* log_scales, co
         double dot = 0;
         for (int j = 0; j < 4; ++j) dot += P.qh[j] * gq[j];
         for (int j = 0; j < 4; ++j) d_quats[4 * i + j] = (gq[j] - P.qh[j] * dot) / P.qn;
-        /* J(p), mean2d(p), depth(p) -> p */
-        double dp[3] = {0, 0, 0};
-        double dtx_dpx = P.clx ? 0.0 : 1.0, dtx_dpz = P.clx ? P.tx / z : 0.0;
-        double dty_dpy = P.cly ? 0.0 : 1.0, dty_dpz = P.cly ? P.ty / z : 0.0;
-        dp[2] += dJ[0][0] * (-k.fx / (z * z)) + dJ[1][1] * (-k.fy / (z * z));
-        dp[0] += dJ[0][2] * (-k.fx / (z * z)) * dtx_dpx;
-        dp[2] += dJ[0][2] * (-k.fx / (z * z) * dtx_dpz + 2.0 * k.fx * P.tx / (z * z * z));
-        dp[1] += dJ[1][2] * (-k.fy / (z * z)) * dty_dpy;
-        dp[2] += dJ[1][2] * (-k.fy / (z * z) * dty_dpz + 2.0 * k.fy * P.ty / (z * z * z));
-        double gmx = d_mean2d[2 * i], gmy = d_mean2d[2 * i + 1];
-        dp[0] += gmx * k.fx / z;
-        dp[2] += -gmx * k.fx * P.p[0] / (z * z);
-        dp[1] += gmy * k.fy / z;
-        dp[2] += -gmy * k.fy * P.p[1] / (z * z);
-        dp[2] += d_depth[i];
         for (int j = 0; j < 3; ++j)
             d_means[3 * i + j] = k.Rv[0][j] * dp[0] + k.Rv[1][j] * dp[1] + k.Rv[2][j] * dp[2];
+    }
+    return 0;
+}
+
+/*
+ * Gradient with respect to the camera pose (Eq. (tracking): the map is frozen
+ * and the extrinsics are optimised).  The world-to-camera pose T is perturbed
+ * on the left, T(xi) = exp(xi^) T with xi = (rho, phi), so to first order
+ * p -> p + rho + phi x p and Sigma_cam -> Sigma_cam + phi^ Sigma_cam -
+ * Sigma_cam phi^.  Summed over the Gaussians:
+ *   dL/drho = sum_i dL/dp_i,
+ *   dL/dphi = sum_i [ p_i x dL/dp_i + axial(Sc_i G_i - G_i Sc_i) ],
+ * G_i = dL/dSigma_cam,i, axial(A) = (A_23 - A_32, A_31 - A_13, A_12 - A_21).
+ * d_pose[6] = (dL/drho, dL/dphi).
+ */
+int orc_pose_grad(int64_t n, const double* means, const double* log_scales, const double* quats,
+                  const double* opac, const double* cam, const double* d_mean2d, const double* d_conic,
+                  const double* d_depth, double* d_pose) {
+    cam_t k; read_cam(cam, &k);
+    for (int j = 0; j < 6; ++j) d_pose[j] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        proj_t P;
+        project_one(means + 3 * i, log_scales + 3 * i, quats + 4 * i, opac[i], &k, &P);
+        if (P.culled) continue;
+        double dp[3], G[3][3];
+        adjoint_cam(&k, &P, d_conic + 3 * i, d_mean2d[2 * i], d_mean2d[2 * i + 1], d_depth[i], dp, G);
+        double A[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0;
+                for (int m = 0; m < 3; ++m) acc += P.Sc[r][m] * G[m][c] - G[r][m] * P.Sc[m][c];
+                A[r][c] = acc;
+            }
+        const double* p = P.p;
+        d_pose[0] += dp[0]; d_pose[1] += dp[1]; d_pose[2] += dp[2];
+        d_pose[3] += p[1] * dp[2] - p[2] * dp[1] + (A[1][2] - A[2][1]);
+        d_pose[4] += p[2] * dp[0] - p[0] * dp[2] + (A[2][0] - A[0][2]);
+        d_pose[5] += p[0] * dp[1] - p[1] * dp[0] + (A[0][1] - A[1][0]);
     }
     return 0;
 }
