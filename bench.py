@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-semantic", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for profiles)")
@@ -246,6 +247,9 @@ def main():
         "roofline": roof,
     }
 
+    if not args.no_semantic:
+        result["semantic_phase"] = semantic_phase(xgs, synth, dev, G)
+
     if not args.no_serve:
         del X, Xh, G
         torch.cuda.empty_cache()
@@ -255,6 +259,74 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, synth)
     print(json.dumps(result), flush=True)
+
+
+def semantic_phase(xgs, synth, dev, G, reps: int = 10):
+    """Semantic phase (geometry frozen): 300k-Gaussian room at 640x480, L = 16
+    mixture weights over a 16 x 512 codebook, targets = the 512 x 480 x 640
+    bilinear grid sample, blocky validity mask.  Per stage: softmax, render
+    forward, fused decode + masked loss, feature-only backward, softmax
+    backward (HIP events, mean of `reps` runs after 3 warm-up runs)."""
+    import torch
+    log("semantic phase: 300k room, 640x480, L=16, D=512")
+    t = lambda a, dt=np.float32: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
+    scene = synth.room_scene(300_000, seed=2, c_sem=16)
+    rng = np.random.default_rng(11)
+    L, D = 16, 512
+    z = t(rng.standard_normal((scene.n, L)) * 2)
+    E = t(rng.standard_normal((L, D)))
+    yy, xx = np.mgrid[0:480, 0:640]
+    V = t((((yy // 60) + (xx // 80)) % 3 != 0), np.uint8)
+    g = xgs.Gaussians(t(scene.means), t(scene.log_scales), t(scene.quats), t(scene.opacity), t(scene.colors),
+                      t(scene.features))
+    cam = xgs.camera_from(synth.room_camera(640, 480, 525.0, synth.room_trajectory(100, seed=10)[7]))
+    p = xgs.xgs_project(g, cam)
+    m = int(p.tiles_touched.to(torch.int64).sum().item())
+    b = xgs.alloc_binning(g.n, m + 1024, cam, dev)
+    xgs.xgs_tile_sort(p, cam, g.n, b)
+    w = torch.empty_like(z)
+    dz = torch.empty_like(z)
+    gw = xgs.Gaussians(g.means, g.log_scales, g.quats, g.opacity, g.colors, w)
+    out = torch.empty((4 + L, 480, 640), device=dev)
+    fT = torch.empty((480, 640), device=dev)
+    nl = torch.empty((480, 640), dtype=torch.int32, device=dev)
+    d_out = torch.empty_like(out)
+    loss = torch.empty(1, device=dev)
+    lws = torch.empty(int(xgs.lib.xgs_semantic_loss_workspace(480, 640)), dtype=torch.uint8, device=dev)
+    grads = xgs.Gaussians.empty_like(gw)
+    bws = torch.empty(int(xgs.lib.xgs_render_bwd_workspace(g.n)), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    names = ["softmax", "render_fwd", "decode_loss", "render_bwd_features", "softmax_bwd"]
+
+    def run(evs):
+        evs[0].record(stream)
+        xgs.xgs_semantic_softmax(z, w)
+        evs[1].record(stream)
+        xgs.xgs_render_fwd(gw, p, b, cam, out=out, final_T=fT, n_last=nl)
+        evs[2].record(stream)
+        xgs.xgs_semantic_loss(out, E, G, V, 1.0, d_out=d_out, loss=loss, workspace=lws)
+        evs[3].record(stream)
+        xgs.xgs_render_bwd(gw, p, b, cam, d_out, fT, nl, flags=xgs.BWD_FEATURES_ONLY, grads=grads, workspace=bws)
+        evs[4].record(stream)
+        xgs.xgs_semantic_softmax_bwd(w, grads.features, dz)
+        evs[5].record(stream)
+
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+    for _ in range(3):
+        run(mk())
+    torch.cuda.synchronize()
+    evs_all = [mk() for _ in range(reps)]
+    for evs in evs_all:
+        run(evs)
+    torch.cuda.synchronize()
+    ms = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs_all])) for i, n in enumerate(names)}
+    P_ = 480 * 640
+    loss_bytes = 2 * D * P_ * 4 + L * P_ * 4 + P_ + (4 + L) * P_ * 4
+    return {"workload": "300k-Gaussian room, 640x480, L=16 mixture weights, D=512 targets, geometry frozen",
+            "ms": {k: round(v, 4) for k, v in ms.items()}, "total_ms": round(sum(ms.values()), 4),
+            "instances": m, "loss": float(loss.item()),
+            "decode_loss_GBps": round(loss_bytes / (ms["decode_loss"] * 1e-3) / 1e9, 1),
+            "decode_loss_bytes": loss_bytes}
 
 
 def serving(xgs, synth, dev, n_requests):

@@ -212,6 +212,32 @@ xgs_status xgs_grid_sample(const float* P, int32_t D, int32_t Hf, int32_t Wf, in
                            int32_t W, int32_t stride, int32_t off_y, int32_t off_x, int32_t mode,
                            float* G, uint8_t* V, xgs_stream_t stream);
 
+/* ----------------------------------------- f2: camera-pose gradient (Eq. (tracking))
+ * dL/dxi for the left perturbation T(xi) = exp(xi^) T of the world-to-camera
+ * pose, xi = (rho, phi) (translation, rotation), at xi = 0:
+ *   d_pose[0..2] = sum_i dL/dp_i,
+ *   d_pose[3..5] = sum_i [ p_i x dL/dp_i + axial(Sc_i G_i - G_i Sc_i) ],
+ * p_i camera-space mean, Sc_i camera covariance, G_i = dL/dSc_i,
+ * axial(A) = (A_23 - A_32, A_31 - A_13, A_12 - A_21).
+ * Call after xgs_render_bwd (XGS_BWD_ALL) on the same stream with the same
+ * g, p, cam and ws: it reads the per-Gaussian image-space adjoints that pass
+ * leaves in ws.  d_pose: 6 device floats.  Deterministic (fixed order). */
+xgs_status xgs_pose_grad(const xgs_gaussians* g, const xgs_projected* p, const xgs_camera* cam,
+                         const void* ws, size_t ws_bytes, float* d_pose, xgs_stream_t stream);
+
+/* Tracking loss (Eq. (loss_track), L_photo read as L1):
+ *   loss = (1/(3 P)) sum_x sum_{c<3} |out_c(x) - image_c(x)|
+ *        + lambda_d (1/P_D) sum_{x: depth(x) > 0} |out_3(x) - depth(x)|,
+ * P = Hs Ws, P_D = #pixels with depth > 0 (no depth term if P_D = 0 or
+ * depth == NULL).  out [C][Hs][Ws] (C >= 4: RGB, depth, semantic), image
+ * [3][Hs][Ws], depth [Hs][Ws].  Writes *loss (device float) and d_out
+ * [C][Hs][Ws] = dL/dout (zero on channels >= 4).  Deterministic.  ws:
+ * xgs_tracking_loss_workspace(Hs, Ws) bytes, 256-byte aligned. */
+size_t xgs_tracking_loss_workspace(int32_t Hs, int32_t Ws);
+xgs_status xgs_tracking_loss(const float* out, int32_t C, int32_t Hs, int32_t Ws, const float* image,
+                             const float* depth, float lambda_d, float* d_out, float* loss, void* ws,
+                             size_t ws_bytes, xgs_stream_t stream);
+
 /* ------------------------------------------- f1: semantic phase (Sec. 3.2.2, App. D, App. E)
  * Mixture weights w_i = softmax(z_i) over L codewords (Sec. 3.2.2); z, w,
  * dL/dw, dL/dz are [N][L] row-major FP32, 16-byte aligned; L in

@@ -35,7 +35,7 @@ __all__ = [
     "xgs_project", "xgs_project_posed", "alloc_binning", "xgs_tile_sort", "xgs_render_fwd", "xgs_render_bwd",
     "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_stage", "xgs_vq_candidates", "xgs_vq_rescore",
     "vq_assign_workspace", "xgs_vq_ema_update", "xgs_semantic_softmax", "xgs_semantic_softmax_bwd",
-    "xgs_semantic_loss", "semantic_step", "render",
+    "xgs_semantic_loss", "semantic_step", "xgs_pose_grad", "xgs_tracking_loss", "tracking_step", "render",
 ]
 
 
@@ -283,6 +283,45 @@ def xgs_vq_rescore(X: torch.Tensor, E: torch.Tensor, workspace: torch.Tensor, id
     check(lib.xgs_vq_rescore(_ptr(X), N, D, _ptr(E), K, _ptr(idx), _ptr(dist), _ptr(workspace), workspace.numel(),
                              _stream(stream)), "xgs_vq_rescore")
     return idx, dist
+
+
+def xgs_pose_grad(g: Gaussians, p: Projected, cam, workspace: torch.Tensor, d_pose=None, stream=None):
+    """dL/dxi (translation, rotation) of the left pose perturbation; call after
+    xgs_render_bwd(..., workspace=workspace) on the same stream."""
+    c = camera_from(cam)
+    d_pose = d_pose if d_pose is not None else torch.empty(6, dtype=torch.float32, device=g.means.device)
+    gs, ps = g.struct(), p.struct()
+    check(lib.xgs_pose_grad(ctypes.byref(gs), ctypes.byref(ps), ctypes.byref(c), _ptr(workspace), workspace.numel(),
+                            _ptr(d_pose), _stream(stream)), "xgs_pose_grad")
+    return d_pose
+
+
+def xgs_tracking_loss(out: torch.Tensor, image: torch.Tensor, depth=None, lam_d: float = 1.0, d_out=None, loss=None,
+                      workspace=None, stream=None):
+    C, Hs, Ws = out.shape
+    d_out = d_out if d_out is not None else torch.empty_like(out)
+    loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=out.device)
+    if workspace is None:
+        workspace = torch.empty(int(lib.xgs_tracking_loss_workspace(Hs, Ws)), dtype=torch.uint8, device=out.device)
+    check(lib.xgs_tracking_loss(_ptr(out), C, Hs, Ws, _ptr(image), _ptr(depth), float(lam_d), _ptr(d_out), _ptr(loss),
+                                _ptr(workspace), workspace.numel(), _stream(stream)), "xgs_tracking_loss")
+    return loss, d_out
+
+
+def tracking_step(g: Gaussians, p: Projected, b: Binning, cam, image: torch.Tensor, depth=None, lam_d: float = 1.0,
+                  workspace=None, stream=None):
+    """One tracking evaluation with the map frozen (Eq. (tracking)): render,
+    L1 photometric + depth loss, backward, and the pose gradient.  ``p`` and
+    ``b`` must come from xgs_project / xgs_tile_sort at ``cam``.  Returns
+    (loss [1], dL/dxi [6], rendered map)."""
+    out, fT, nl = xgs_render_fwd(g, p, b, cam, stream=stream)
+    loss, d_out = xgs_tracking_loss(out, image, depth, lam_d, stream=stream)
+    need = int(lib.xgs_render_bwd_workspace(g.n))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=g.means.device)
+    xgs_render_bwd(g, p, b, cam, d_out, fT, nl, workspace=workspace, stream=stream)
+    d_pose = xgs_pose_grad(g, p, cam, workspace, stream=stream)
+    return loss, d_pose, out
 
 
 def xgs_semantic_softmax(z: torch.Tensor, w=None, stream=None) -> torch.Tensor:

@@ -72,6 +72,11 @@ SIGNATURES = {
     "xgs_vq_candidates": (c_int32, [c_int64, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
     "xgs_vq_rescore": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                                  c_size_t, c_void_p]),
+    "xgs_pose_grad": (c_int32, [P(XgsGaussians), P(XgsProjected), P(XgsCamera), c_void_p, c_size_t, c_void_p,
+                                c_void_p]),
+    "xgs_tracking_loss_workspace": (c_size_t, [c_int32, c_int32]),
+    "xgs_tracking_loss": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_float, c_void_p,
+                                    c_void_p, c_void_p, c_size_t, c_void_p]),
     "xgs_semantic_softmax": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "xgs_semantic_softmax_bwd": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "xgs_semantic_loss_workspace": (c_size_t, [c_int32, c_int32]),

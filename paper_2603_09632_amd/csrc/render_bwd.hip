@@ -296,6 +296,90 @@ struct CamDevB {
     float R[9], t[3];
 };
 
+// Adjoint of one Gaussian's projection down to the camera frame (App. A):
+// recomputes p = Rv mu + t, R(q), the scales, M = R S, Sigma_cam = (Rv M)
+// (Rv M)^T and J at the guarded p, then carries dL/dmean2d, dL/dconic and
+// dL/ddepth (the workspace row) to dL/dp and dL/dSigma_cam.
+struct CamAdj {
+    float p[3];
+    float R[3][3], s[3], M[3][3], Sc[3][3];
+    float dSc[3][3], dp[3];
+    float q[4], inv;
+};
+
+__device__ __forceinline__ void cam_adjoint(int64_t i, const float* __restrict__ means,
+                                            const float* __restrict__ log_scales,
+                                            const float4* __restrict__ quats, const float4* __restrict__ splat,
+                                            const float* __restrict__ gw, const CamDevB& c, CamAdj& a) {
+    const float gmx = gw[GW_MX], gmy = gw[GW_MY];
+    const float gA = gw[GW_A], gB = gw[GW_B], gC = gw[GW_C], gd = gw[GW_DEPTH];
+    const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+    const float px = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
+    const float py = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
+    const float pz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
+    a.p[0] = px; a.p[1] = py; a.p[2] = pz;
+    float4 q = quats[i];
+    const float qn = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+    a.inv = 1.f / qn;
+    const float w = q.x * a.inv, x = q.y * a.inv, y = q.z * a.inv, z = q.w * a.inv;
+    a.q[0] = w; a.q[1] = x; a.q[2] = y; a.q[3] = z;
+    const float R[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
+                           {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
+                           {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) a.R[r][k] = R[r][k];
+    a.s[0] = __expf(log_scales[3 * i]); a.s[1] = __expf(log_scales[3 * i + 1]); a.s[2] = __expf(log_scales[3 * i + 2]);
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) a.M[r][k] = R[r][k] * a.s[k];
+    // Sigma_cam = (Rv M)(Rv M)^T
+    float TM[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k)
+            TM[r][k] = c.R[3 * r] * a.M[0][k] + c.R[3 * r + 1] * a.M[1][k] + c.R[3 * r + 2] * a.M[2][k];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) a.Sc[r][k] = TM[r][0] * TM[k][0] + TM[r][1] * TM[k][1] + TM[r][2] * TM[k][2];
+    const float iz = 1.f / pz;
+    const float u = px * iz, v = py * iz;
+    const bool clx = u < -c.limx || u > c.limx, cly = v < -c.limy || v > c.limy;
+    const float tx = fminf(fmaxf(u, -c.limx), c.limx) * pz;
+    const float ty = fminf(fmaxf(v, -c.limy), c.limy) * pz;
+    const float J[2][3] = {{c.fx * iz, 0.f, -c.fx * tx * iz * iz}, {0.f, c.fy * iz, -c.fy * ty * iz * iz}};
+    // conic = (A, B, C) from the splat record; dSigma' = -K Ghat K
+    const float4 s0 = splat[2 * i], s1 = splat[2 * i + 1];
+    const float K00 = s0.z, K01 = s0.w, K11 = s1.x;
+    const float G00 = gA, G01 = 0.5f * gB, G11 = gC;
+    const float KG00 = K00 * G00 + K01 * G01, KG01 = K00 * G01 + K01 * G11;
+    const float KG10 = K01 * G00 + K11 * G01, KG11 = K01 * G01 + K11 * G11;
+    const float dS00 = -(KG00 * K00 + KG01 * K01);
+    const float dS01 = -(KG00 * K01 + KG01 * K11);
+    const float dS11 = -(KG10 * K01 + KG11 * K11);
+    const float dS[2][2] = {{dS00, dS01}, {dS01, dS11}};
+    // dSc = J^T dS J ; dJ = 2 dS J Sc
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            float acc = 0.f;
+            for (int aa = 0; aa < 2; ++aa)
+                for (int bb = 0; bb < 2; ++bb) acc += J[aa][r] * dS[aa][bb] * J[bb][k];
+            a.dSc[r][k] = acc;
+        }
+    float JSc[2][3];
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 3; ++k) JSc[r][k] = J[r][0] * a.Sc[0][k] + J[r][1] * a.Sc[1][k] + J[r][2] * a.Sc[2][k];
+    float dJ[2][3];
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 3; ++k) dJ[r][k] = 2.f * (dS[r][0] * JSc[0][k] + dS[r][1] * JSc[1][k]);
+    // J(p), mean2d(p), depth(p) -> p
+    const float iz2 = iz * iz, iz3 = iz2 * iz;
+    const float dtx_dpx = clx ? 0.f : 1.f, dtx_dpz = clx ? tx * iz : 0.f;
+    const float dty_dpy = cly ? 0.f : 1.f, dty_dpz = cly ? ty * iz : 0.f;
+    a.dp[0] = dJ[0][2] * (-c.fx * iz2) * dtx_dpx + gmx * c.fx * iz;
+    a.dp[1] = dJ[1][2] * (-c.fy * iz2) * dty_dpy + gmy * c.fy * iz;
+    a.dp[2] = dJ[0][0] * (-c.fx * iz2) + dJ[1][1] * (-c.fy * iz2) +
+              dJ[0][2] * (-c.fx * iz2 * dtx_dpz + 2.f * c.fx * tx * iz3) +
+              dJ[1][2] * (-c.fy * iz2 * dty_dpz + 2.f * c.fy * ty * iz3) - gmx * c.fx * px * iz2 -
+              gmy * c.fy * py * iz2 + gd;
+}
+
 // Per-Gaussian chain rule from (mean2d, conic, depth) to (mean, log-scale,
 // quaternion); the forward quantities are recomputed from the parameters.
 __global__ void __launch_bounds__(256) project_bwd_kernel(
@@ -308,69 +392,13 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     float gm[3] = {0.f, 0.f, 0.f}, gl[3] = {0.f, 0.f, 0.f};
     float4 gq = make_float4(0.f, 0.f, 0.f, 0.f);
     if (radius[i] > 0) {
-        const float* gw = geo + (size_t)i * GW_STRIDE;
-        const float gmx = gw[GW_MX], gmy = gw[GW_MY];
-        const float gA = gw[GW_A], gB = gw[GW_B], gC = gw[GW_C], gd = gw[GW_DEPTH];
-        const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
-        const float px = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
-        const float py = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
-        const float pz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
-        float4 q = quats[i];
-        const float qn = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
-        const float inv = 1.f / qn;
-        const float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
-        float R[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
-                         {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
-                         {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-        const float s[3] = {__expf(log_scales[3 * i]), __expf(log_scales[3 * i + 1]),
-                            __expf(log_scales[3 * i + 2])};
-        float M[3][3];
-        for (int r = 0; r < 3; ++r)
-            for (int k = 0; k < 3; ++k) M[r][k] = R[r][k] * s[k];
-        // Sigma_cam = (Rv M)(Rv M)^T
-        float TM[3][3];
-        for (int r = 0; r < 3; ++r)
-            for (int k = 0; k < 3; ++k)
-                TM[r][k] = c.R[3 * r] * M[0][k] + c.R[3 * r + 1] * M[1][k] + c.R[3 * r + 2] * M[2][k];
-        float Sc[3][3];
-        for (int r = 0; r < 3; ++r)
-            for (int k = 0; k < 3; ++k) Sc[r][k] = TM[r][0] * TM[k][0] + TM[r][1] * TM[k][1] + TM[r][2] * TM[k][2];
-        const float iz = 1.f / pz;
-        const float u = px * iz, v = py * iz;
-        const bool clx = u < -c.limx || u > c.limx, cly = v < -c.limy || v > c.limy;
-        const float tx = fminf(fmaxf(u, -c.limx), c.limx) * pz;
-        const float ty = fminf(fmaxf(v, -c.limy), c.limy) * pz;
-        const float J[2][3] = {{c.fx * iz, 0.f, -c.fx * tx * iz * iz}, {0.f, c.fy * iz, -c.fy * ty * iz * iz}};
-        // conic = (A, B, C) from the splat record; dSigma' = -K Ghat K
-        const float4 s0 = splat[2 * i], s1 = splat[2 * i + 1];
-        const float K00 = s0.z, K01 = s0.w, K11 = s1.x;
-        const float G00 = gA, G01 = 0.5f * gB, G11 = gC;
-        const float KG00 = K00 * G00 + K01 * G01, KG01 = K00 * G01 + K01 * G11;
-        const float KG10 = K01 * G00 + K11 * G01, KG11 = K01 * G01 + K11 * G11;
-        const float dS00 = -(KG00 * K00 + KG01 * K01);
-        const float dS01 = -(KG00 * K01 + KG01 * K11);
-        const float dS11 = -(KG10 * K01 + KG11 * K11);
-        const float dS[2][2] = {{dS00, dS01}, {dS01, dS11}};
-        // dSc = J^T dS J ; dJ = 2 dS J Sc
-        float dSc[3][3];
-        for (int r = 0; r < 3; ++r)
-            for (int k = 0; k < 3; ++k) {
-                float acc = 0.f;
-                for (int a = 0; a < 2; ++a)
-                    for (int bb = 0; bb < 2; ++bb) acc += J[a][r] * dS[a][bb] * J[bb][k];
-                dSc[r][k] = acc;
-            }
-        float JSc[2][3];
-        for (int r = 0; r < 2; ++r)
-            for (int k = 0; k < 3; ++k) JSc[r][k] = J[r][0] * Sc[0][k] + J[r][1] * Sc[1][k] + J[r][2] * Sc[2][k];
-        float dJ[2][3];
-        for (int r = 0; r < 2; ++r)
-            for (int k = 0; k < 3; ++k) dJ[r][k] = 2.f * (dS[r][0] * JSc[0][k] + dS[r][1] * JSc[1][k]);
+        CamAdj a;
+        cam_adjoint(i, means, log_scales, quats, splat, geo + (size_t)i * GW_STRIDE, c, a);
         // dSigma = Rv^T dSc Rv
         float tmp[3][3], dSig[3][3];
         for (int r = 0; r < 3; ++r)
             for (int k = 0; k < 3; ++k)
-                tmp[r][k] = c.R[r] * dSc[0][k] + c.R[3 + r] * dSc[1][k] + c.R[6 + r] * dSc[2][k];
+                tmp[r][k] = c.R[r] * a.dSc[0][k] + c.R[3 + r] * a.dSc[1][k] + c.R[6 + r] * a.dSc[2][k];
         for (int r = 0; r < 3; ++r)
             for (int k = 0; k < 3; ++k)
                 dSig[r][k] = tmp[r][0] * c.R[k] + tmp[r][1] * c.R[3 + k] + tmp[r][2] * c.R[6 + k];
@@ -379,12 +407,13 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         for (int k = 0; k < 3; ++k) {
             float ds = 0.f;
             for (int r = 0; r < 3; ++r) {
-                const float dM = 2.f * (dSig[r][0] * M[0][k] + dSig[r][1] * M[1][k] + dSig[r][2] * M[2][k]);
-                ds += dM * R[r][k];
-                dR[r][k] = dM * s[k];
+                const float dM = 2.f * (dSig[r][0] * a.M[0][k] + dSig[r][1] * a.M[1][k] + dSig[r][2] * a.M[2][k]);
+                ds += dM * a.R[r][k];
+                dR[r][k] = dM * a.s[k];
             }
-            gl[k] = ds * s[k];
+            gl[k] = ds * a.s[k];
         }
+        const float w = a.q[0], x = a.q[1], y = a.q[2], z = a.q[3];
         float g0 = 2.f * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
         float g1 = 2.f * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.f * x * dR[1][1] - w * dR[1][2] +
                           z * dR[2][0] + w * dR[2][1] - 2.f * x * dR[2][2]);
@@ -393,22 +422,66 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         float g3 = 2.f * (-2.f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.f * z * dR[1][1] +
                           y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
         const float dot = w * g0 + x * g1 + y * g2 + z * g3;
-        gq = make_float4((g0 - w * dot) * inv, (g1 - x * dot) * inv, (g2 - y * dot) * inv, (g3 - z * dot) * inv);
-        // J(p), mean2d(p), depth(p) -> p -> mu
-        const float iz2 = iz * iz, iz3 = iz2 * iz;
-        const float dtx_dpx = clx ? 0.f : 1.f, dtx_dpz = clx ? tx * iz : 0.f;
-        const float dty_dpy = cly ? 0.f : 1.f, dty_dpz = cly ? ty * iz : 0.f;
-        float dpx = dJ[0][2] * (-c.fx * iz2) * dtx_dpx + gmx * c.fx * iz;
-        float dpy = dJ[1][2] * (-c.fy * iz2) * dty_dpy + gmy * c.fy * iz;
-        float dpz = dJ[0][0] * (-c.fx * iz2) + dJ[1][1] * (-c.fy * iz2) +
-                    dJ[0][2] * (-c.fx * iz2 * dtx_dpz + 2.f * c.fx * tx * iz3) +
-                    dJ[1][2] * (-c.fy * iz2 * dty_dpz + 2.f * c.fy * ty * iz3) -
-                    gmx * c.fx * px * iz2 - gmy * c.fy * py * iz2 + gd;
-        for (int k = 0; k < 3; ++k) gm[k] = c.R[k] * dpx + c.R[3 + k] * dpy + c.R[6 + k] * dpz;
+        gq = make_float4((g0 - w * dot) * a.inv, (g1 - x * dot) * a.inv, (g2 - y * dot) * a.inv,
+                         (g3 - z * dot) * a.inv);
+        // p -> mu
+        for (int k = 0; k < 3; ++k) gm[k] = c.R[k] * a.dp[0] + c.R[3 + k] * a.dp[1] + c.R[6 + k] * a.dp[2];
     }
     d_means[3 * i] = gm[0]; d_means[3 * i + 1] = gm[1]; d_means[3 * i + 2] = gm[2];
     d_ls[3 * i] = gl[0]; d_ls[3 * i + 1] = gl[1]; d_ls[3 * i + 2] = gl[2];
     d_quats[i] = gq;
+}
+
+// Camera-pose gradient (Eq. (tracking): extrinsics optimised with the map
+// frozen) for the left perturbation T(xi) = exp(xi^) T, xi = (rho, phi):
+// p -> p + rho + phi x p and Sigma_cam -> Sigma_cam + phi^ Sigma_cam -
+// Sigma_cam phi^, so per Gaussian dL/drho = dL/dp and
+// dL/dphi = p x dL/dp + axial(Sc G - G Sc), G = dL/dSigma_cam,
+// axial(A) = (A_23 - A_32, A_31 - A_13, A_12 - A_21).  Each workgroup sums
+// its 256 Gaussians in a fixed tree order into partial[block][6].
+__global__ void __launch_bounds__(256) pose_grad_kernel(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const int32_t* __restrict__ radius, const float4* __restrict__ splat,
+    const float* __restrict__ geo, CamDevB c, float* __restrict__ partial) {
+    __shared__ float red[4][6];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (i < n && radius[i] > 0) {
+        CamAdj a;
+        cam_adjoint(i, means, log_scales, quats, splat, geo + (size_t)i * GW_STRIDE, c, a);
+        float A[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) {
+                float acc = 0.f;
+                for (int m = 0; m < 3; ++m) acc += a.Sc[r][m] * a.dSc[m][k] - a.dSc[r][m] * a.Sc[m][k];
+                A[r][k] = acc;
+            }
+        const float* p = a.p;
+        const float* dp = a.dp;
+        v[0] = dp[0]; v[1] = dp[1]; v[2] = dp[2];
+        v[3] = p[1] * dp[2] - p[2] * dp[1] + (A[1][2] - A[2][1]);
+        v[4] = p[2] * dp[0] - p[0] * dp[2] + (A[2][0] - A[0][2]);
+        v[5] = p[0] * dp[1] - p[1] * dp[0] + (A[0][1] - A[1][0]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        for (int o = 32; o >= 1; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) red[threadIdx.x >> 6][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6)
+        partial[(size_t)blockIdx.x * 6 + threadIdx.x] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(64) pose_total_kernel(const float* __restrict__ partial, int64_t nb,
+                                                       float* __restrict__ d_pose) {
+    const int k = threadIdx.x;
+    if (k >= 6) return;
+    float s = 0.f;
+    for (int64_t b = 0; b < nb; ++b) s += partial[(size_t)b * 6 + k];
+    d_pose[k] = s;
 }
 
 template <int CS, bool GEO, bool EXACT = true>
@@ -446,13 +519,28 @@ static void dispatch_bwd(const xgs_gaussians* g, const xgs_projected* p, const x
     }
 }
 
+static CamDevB cam_dev_b(const xgs_camera& cam) {
+    CamDevB c;
+    c.fx = cam.fx; c.fy = cam.fy; c.near_ = cam.near_plane;
+    c.limx = kGuard * (0.5f * cam.width) / cam.fx;
+    c.limy = kGuard * (0.5f * cam.height) / cam.fy;
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) c.R[3 * r + k] = cam.viewmat[4 * r + k];
+        c.t[r] = cam.viewmat[4 * r + 3];
+    }
+    return c;
+}
+
 }  // namespace xgs
 
 using namespace xgs;
 
+static size_t pose_blocks(int64_t n) { return (size_t)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+
 extern "C" size_t xgs_render_bwd_workspace(int64_t n) {
     Carve c(nullptr);
     c.take<float>((size_t)(n > 0 ? n : 1) * GW_STRIDE);
+    c.take<float>(pose_blocks(n) * 6);
     return c.total();
 }
 
@@ -500,14 +588,7 @@ extern "C" xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected
         if ((s = fill_f32(geo, GW_STRIDE * g->n, 0.f, st))) return s;
         dispatch_bwd<true>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
         if ((s = check_launch("xgs_render_bwd pixels"))) return s;
-        CamDevB c;
-        c.fx = cam->fx; c.fy = cam->fy; c.near_ = cam->near_plane;
-        c.limx = kGuard * (0.5f * cam->width) / cam->fx;
-        c.limy = kGuard * (0.5f * cam->height) / cam->fy;
-        for (int r = 0; r < 3; ++r) {
-            for (int k = 0; k < 3; ++k) c.R[3 * r + k] = cam->viewmat[4 * r + k];
-            c.t[r] = cam->viewmat[4 * r + 3];
-        }
+        const CamDevB c = cam_dev_b(*cam);
         hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)((g->n + 255) / 256)), dim3(256), 0, st, g->n,
                            g->means, g->log_scales, reinterpret_cast<const float4*>(g->quats), p->radius,
                            reinterpret_cast<const float4*>(p->splat), geo, c, gr->means, gr->log_scales,
@@ -516,4 +597,27 @@ extern "C" xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected
     }
     dispatch_bwd<false>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
     return check_launch("xgs_render_bwd features");
+}
+
+extern "C" xgs_status xgs_pose_grad(const xgs_gaussians* g, const xgs_projected* p, const xgs_camera* cam,
+                                    const void* ws, size_t ws_bytes, float* d_pose, xgs_stream_t stream) {
+    clear_error();
+    if (!g || !p || !cam || !d_pose) return fail(XGS_ERR_INVALID_ARG, "xgs_pose_grad: null argument");
+    if (xgs_status s = validate_camera(cam)) return s;
+    if (!aligned(ws, 256)) return fail(XGS_ERR_INVALID_ARG, "xgs_pose_grad: workspace must be 256-byte aligned");
+    if (!ws || ws_bytes < xgs_render_bwd_workspace(g->n))
+        return fail(XGS_ERR_CAPACITY, "xgs_pose_grad: workspace too small");
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !p->splat || !p->radius))
+        return fail(XGS_ERR_INVALID_ARG, "xgs_pose_grad: null Gaussian array");
+    Carve cv(const_cast<void*>(ws));
+    const float* geo = cv.take<float>((size_t)(g->n > 0 ? g->n : 1) * GW_STRIDE);
+    float* partial = cv.take<float>(pose_blocks(g->n) * 6);
+    hipStream_t st = (hipStream_t)stream;
+    if (g->n == 0) return fill_f32(d_pose, 6, 0.f, st);
+    const size_t nb = pose_blocks(g->n);
+    hipLaunchKernelGGL(pose_grad_kernel, dim3((unsigned)nb), dim3(256), 0, st, g->n, g->means, g->log_scales,
+                       reinterpret_cast<const float4*>(g->quats), p->radius,
+                       reinterpret_cast<const float4*>(p->splat), geo, cam_dev_b(*cam), partial);
+    hipLaunchKernelGGL(pose_total_kernel, dim3(1), dim3(64), 0, st, partial, (int64_t)nb, d_pose);
+    return check_launch("xgs_pose_grad");
 }
