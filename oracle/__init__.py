@@ -529,3 +529,60 @@ def se3_exp(xi):
     T[:3, :3] = R
     T[:3, 3] = V @ rho
     return T
+
+
+# ------------------------------------------------ region targets, occluders
+def region_targets(S, Phi, stride: int = 1, off_y: int = 0, off_x: int = 0):
+    """App. D Eq. (target_discrete): G*[:, m, n] = Phi[S(u, v)] and
+    V = [S(u, v) != -1] at (u, v) = (off_y + m s, off_x + n s) on the
+    ceil(H/s) x ceil(W/s) grid; zero target and V = 0 where S = -1 or (u, v)
+    lies outside the image.  Reading: labels outside [0, R) are treated as
+    unannotated.  Straight loops (the definition)."""
+    S = np.asarray(S)
+    Phi = _f64(Phi)
+    H, W = S.shape
+    R, D = Phi.shape
+    hs, ws = -(-H // stride), -(-W // stride)
+    G = np.zeros((D, hs, ws))
+    V = np.zeros((hs, ws), np.uint8)
+    for m in range(hs):
+        u = off_y + m * stride
+        for n in range(ws):
+            v = off_x + n * stride
+            if u >= H or v >= W:
+                continue
+            lab = int(S[u, v])
+            if 0 <= lab < R:
+                G[:, m, n] = Phi[lab]
+                V[m, n] = 1
+    return G, V
+
+
+def occluder_mask(mean2d, depth, visible, depth_map, margin: float = 0.1):
+    """Occluder pruning (Sec. 3.2.1 mapping; relative margin 10%, Sec. 4.1).
+    Reading: Gaussian i is an occluder when it is visible, the depth map is
+    positive at the pixel holding its projected mean (floor of mean2d, inside
+    the image), and its camera depth is below (1 - margin) times that depth.
+    Inputs in the caller's precision; the comparison runs in that precision
+    (binary32 inputs: binary32, the kernel's)."""
+    mean2d = np.asarray(mean2d)
+    depth = np.asarray(depth)
+    Dm = np.asarray(depth_map)
+    H, W = Dm.shape
+    n = depth.shape[0]
+    out = np.zeros(n, np.uint8)
+    one = depth.dtype.type(1)
+    keep = one - depth.dtype.type(margin)
+    for i in range(n):
+        if not visible[i]:
+            continue
+        x, y = mean2d[i, 0], mean2d[i, 1]
+        if not (x >= 0 and y >= 0):
+            continue
+        c, r = int(np.floor(x)), int(np.floor(y))
+        if r >= H or c >= W:
+            continue
+        d = Dm[r, c]
+        if d > 0 and depth[i] < keep * d:
+            out[i] = 1
+    return out
