@@ -263,6 +263,27 @@ xgs_status xgs_semantic_loss(const float* wmap, int32_t L, int32_t Hs, int32_t W
                              const float* Gstar, const uint8_t* V, float lambda, float* d_out, float* loss,
                              void* ws, size_t ws_bytes, xgs_stream_t stream);
 
+/* ------------------------------------------------- f4: region targets, occluders
+ * App. D, Eq. (target_discrete): for the grid pixel (m, n) at image pixel
+ * (u, v) = (off_y + m s, off_x + n s): V = [0 <= S(u, v) < R] (labels outside
+ * [0, R), including -1 = background, count as unannotated) and
+ * G[:, m, n] = Phi[S(u, v)], else 0; V = 0 and G = 0 where u >= H or v >= W.
+ * S [H][W] int32 (full image), Phi [R][D], G [D][H_s][W_s], V [H_s][W_s]
+ * (may be NULL), H_s = ceil(H / s), W_s = ceil(W / s). */
+xgs_status xgs_region_targets(const int32_t* S, int32_t H, int32_t W, const float* Phi, int32_t R, int32_t D,
+                              int32_t stride, int32_t off_y, int32_t off_x, float* G, uint8_t* V,
+                              xgs_stream_t stream);
+
+/* Occluder pruning (Sec. 3.2.1, mapping; relative margin 10% in Sec. 4.1):
+ * prune[i] = 1 when Gaussian i is visible (radius > 0), its projected mean
+ * lies inside the H x W image, the depth map is positive at the pixel
+ * floor(mean2d), and its camera depth is below (1 - margin) times that depth.
+ * p: xgs_project's output for the n Gaussians; depth_map [H][W] FP32 (full
+ * image); prune [n] u8; *count (device u64) = number pruned.  margin in
+ * [0, 1). */
+xgs_status xgs_occluder_mask(const xgs_projected* p, int64_t n, const float* depth_map, int32_t H, int32_t W,
+                             float margin, uint8_t* prune, uint64_t* count, xgs_stream_t stream);
+
 /* ------------------------------------------------------ a6: VQ assignment
  * a_n = argmin_l ||x_n - E_l||^2 (Sec. 3.2.2), ties to the lowest l.
  * XGS_VQ_FP32: direct FP32 sum of (x - e)^2 over every codeword.

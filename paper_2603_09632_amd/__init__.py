@@ -35,7 +35,8 @@ __all__ = [
     "xgs_project", "xgs_project_posed", "alloc_binning", "xgs_tile_sort", "xgs_render_fwd", "xgs_render_bwd",
     "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_stage", "xgs_vq_candidates", "xgs_vq_rescore",
     "vq_assign_workspace", "xgs_vq_ema_update", "xgs_semantic_softmax", "xgs_semantic_softmax_bwd",
-    "xgs_semantic_loss", "semantic_step", "xgs_pose_grad", "xgs_tracking_loss", "tracking_step", "render",
+    "xgs_semantic_loss", "semantic_step", "xgs_pose_grad", "xgs_tracking_loss", "tracking_step", "xgs_region_targets",
+    "xgs_occluder_mask", "render",
 ]
 
 
@@ -283,6 +284,29 @@ def xgs_vq_rescore(X: torch.Tensor, E: torch.Tensor, workspace: torch.Tensor, id
     check(lib.xgs_vq_rescore(_ptr(X), N, D, _ptr(E), K, _ptr(idx), _ptr(dist), _ptr(workspace), workspace.numel(),
                              _stream(stream)), "xgs_vq_rescore")
     return idx, dist
+
+
+def xgs_region_targets(S: torch.Tensor, Phi: torch.Tensor, stride: int = 1, off_y: int = 0, off_x: int = 0,
+                       G=None, V=None, stream=None):
+    H, W = S.shape
+    R, D = Phi.shape
+    hs, ws = -(-H // stride), -(-W // stride)
+    G = G if G is not None else torch.empty((D, hs, ws), dtype=torch.float32, device=S.device)
+    V = V if V is not None else torch.empty((hs, ws), dtype=torch.uint8, device=S.device)
+    check(lib.xgs_region_targets(_ptr(S), H, W, _ptr(Phi), R, D, int(stride), int(off_y), int(off_x), _ptr(G),
+                                 _ptr(V), _stream(stream)), "xgs_region_targets")
+    return G, V
+
+
+def xgs_occluder_mask(p: "Projected", n: int, depth_map: torch.Tensor, margin: float = 0.1, prune=None, count=None,
+                      stream=None):
+    H, W = depth_map.shape
+    prune = prune if prune is not None else torch.empty(n, dtype=torch.uint8, device=depth_map.device)
+    count = count if count is not None else torch.empty(1, dtype=torch.int64, device=depth_map.device)
+    ps = p.struct()
+    check(lib.xgs_occluder_mask(ctypes.byref(ps), n, _ptr(depth_map), H, W, float(margin), _ptr(prune), _ptr(count),
+                                _stream(stream)), "xgs_occluder_mask")
+    return prune, count
 
 
 def xgs_pose_grad(g: Gaussians, p: Projected, cam, workspace: torch.Tensor, d_pose=None, stream=None):

@@ -77,6 +77,10 @@ SIGNATURES = {
     "xgs_tracking_loss_workspace": (c_size_t, [c_int32, c_int32]),
     "xgs_tracking_loss": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_float, c_void_p,
                                     c_void_p, c_void_p, c_size_t, c_void_p]),
+    "xgs_region_targets": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_int32,
+                                     c_int32, c_void_p, c_void_p, c_void_p]),
+    "xgs_occluder_mask": (c_int32, [P(XgsProjected), c_int64, c_void_p, c_int32, c_int32, c_float, c_void_p,
+                                    c_void_p, c_void_p]),
     "xgs_semantic_softmax": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "xgs_semantic_softmax_bwd": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "xgs_semantic_loss_workspace": (c_size_t, [c_int32, c_int32]),

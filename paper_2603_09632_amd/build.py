@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libxgs.so")
 OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["api.hip", "project.hip", "sort.hip", "tile_sort.hip", "render_fwd.hip", "render_bwd.hip",
-           "grid_sample.hip", "vq.hip", "semantic.hip", "track.hip"]
+           "grid_sample.hip", "vq.hip", "semantic.hip", "track.hip", "targets.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          # packed FP32 instructions stay off: only scalar/float2 code, compiler-chosen
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
