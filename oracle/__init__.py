@@ -54,7 +54,7 @@ def lib():
             build()
         _lib = ctypes.CDLL(_LIB)
         for name in ("orc_project", "orc_composite_fwd", "orc_composite_list", "orc_composite_bwd", "orc_composite_tiles",
-                     "orc_project_bwd", "orc_pose_grad", "orc_vq_assign", "orc_grid_info"):
+                     "orc_project_bwd", "orc_pose_grad", "orc_vq_assign", "orc_vq_confidence", "orc_grid_info"):
             getattr(_lib, name).restype = ctypes.c_int
         _lib.orc_bin.restype = ctypes.c_int64
     return _lib
@@ -586,3 +586,59 @@ def occluder_mask(mean2d, depth, visible, depth_map, margin: float = 0.1):
         if d > 0 and depth[i] < keep * d:
             out[i] = 1
     return out
+
+
+# ------------------------------------------------------------- robust VQ
+# App. C (online VQ codebook details): confidence p_nk = softmax_k(-|x_n - e_k|/tau)
+# (Eq. (confidence_score)), mask m_n = [max_k p_nk >= gamma] (Eq. (mask_confidence))
+# on the samples that update the EMA statistics, hard nearest-neighbour
+# assignments unchanged, dead-code reinitialisation M_k <- x~, N_k <- 1 + eps
+# when N_k < delta (Eq. (dead_code)) with x~ from a reservoir of recent features.
+# Readings: the dead-code test runs on N after the EMA step; the j-th dead
+# code in index order takes reservoir row (offset + j) mod R; the warm start
+# is the masked pass with decay 0 (N = c, M = s).
+
+
+def vq_confidence(X, E, tau: float):
+    """conf[n] = max_k p_nk in FP64 over every codeword."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    E = np.ascontiguousarray(E, dtype=np.float32)
+    N, D = X.shape
+    K = E.shape[0]
+    conf = np.zeros(N)
+    lib().orc_vq_confidence(ctypes.c_int64(N), ctypes.c_int32(D), _p(X), ctypes.c_int32(K), _p(E),
+                            ctypes.c_double(tau), _p(conf))
+    return conf
+
+
+def ema_update_robust(X, idx, conf, gamma: float, N_ema, M_ema, decay: float, eps: float, mode: int,
+                      delta: float, reservoir, offset: int = 0):
+    """Masked EMA step plus dead-code reinitialisation.  conf may be None (all
+    samples count).  Returns (N, M, E, counts, dead_mask)."""
+    X = _f64(X)
+    idx = np.asarray(idx, dtype=np.int64)
+    K, D = M_ema.shape
+    use = np.ones(X.shape[0], bool) if conf is None else (np.asarray(conf) >= gamma)
+    counts = np.zeros(K)
+    sums = np.zeros((K, D))
+    for n in range(X.shape[0]):
+        if use[n]:
+            counts[idx[n]] += 1.0
+            sums[idx[n]] += X[n]
+    N_new = decay * _f64(N_ema) + (1.0 - decay) * counts
+    M_new = decay * _f64(M_ema) + (1.0 - decay) * sums
+    dead = N_new < delta
+    res = _f64(reservoir)
+    j = 0
+    for k in range(K):
+        if dead[k]:
+            M_new[k] = res[(offset + j) % res.shape[0]]
+            N_new[k] = 1.0 + eps
+            j += 1
+    if mode == PAPER:
+        E_new = M_new / (N_new + eps)[:, None]
+    else:
+        tot = N_new.sum()
+        nt = (N_new + eps) / (tot + K * eps) * tot
+        E_new = M_new / nt[:, None]
+    return N_new, M_new, E_new, counts, dead

@@ -648,3 +648,33 @@ int orc_vq_assign(int64_t N, int32_t D, const float* X, int32_t K, const float* 
     }
     return 0;
 }
+
+/*
+ * Confidence of App. C, Eq. (confidence_score): p_nk = softmax_k(-|x_n - e_k| / tau)
+ * with the unsquared distance; conf[n] = max_k p_nk = 1 / sum_j exp(-(d_j - d_min) / tau),
+ * FP64 over every codeword (the shifted sum cannot overflow).
+ */
+int orc_vq_confidence(int64_t N, int32_t D, const float* X, int32_t K, const float* E, double tau,
+                      double* conf) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t nrow = 0; nrow < N; ++nrow) {
+        const float* x = X + nrow * D;
+        double dmin = INFINITY;
+        double* dist = (double*)malloc(sizeof(double) * (size_t)K);
+        for (int32_t l = 0; l < K; ++l) {
+            const float* e = E + (int64_t)l * D;
+            double acc = 0.0;
+            for (int32_t d = 0; d < D; ++d) {
+                double t = (double)x[d] - (double)e[d];
+                acc += t * t;
+            }
+            dist[l] = sqrt(acc);
+            if (dist[l] < dmin) dmin = dist[l];
+        }
+        double s = 0.0;
+        for (int32_t l = 0; l < K; ++l) s += exp(-(dist[l] - dmin) / tau);
+        conf[nrow] = 1.0 / s;
+        free(dist);
+    }
+    return 0;
+}
