@@ -249,6 +249,8 @@ def main():
 
     if not args.no_semantic:
         result["semantic_phase"] = semantic_phase(xgs, synth, dev, G)
+        result["tracking_and_targets"] = tracking_and_targets(xgs, g, p, b, cams[args.warmup + args.steps - 1], out,
+                                                              fT, nl, d_out, grads, bwd_ws, dev)
 
     if not args.no_serve:
         del X, Xh, G
@@ -327,6 +329,58 @@ def semantic_phase(xgs, synth, dev, G, reps: int = 10):
             "instances": m, "loss": float(loss.item()),
             "decode_loss_GBps": round(loss_bytes / (ms["decode_loss"] * 1e-3) / 1e9, 1),
             "decode_loss_bytes": loss_bytes}
+
+
+def tracking_and_targets(xgs, g, p, b, cam, out, fT, nl, d_out, grads, bwd_ws, dev, reps: int = 10):
+    """Tracking pieces on the 1M-Gaussian 1200x680 frame (loss -> backward ->
+    pose gradient), occluder pruning of the 1M Gaussians against a depth map,
+    and region-indexed targets at 640x480 (D = 512, 100 regions)."""
+    import torch
+    log("tracking, occluder pruning, region targets")
+    stream = torch.cuda.current_stream()
+    torch.manual_seed(3)
+    image = (out[:3] + 0.02 * torch.randn_like(out[:3])).contiguous()
+    depth = (out[3] * 1.01).contiguous()
+    loss = torch.empty(1, device=dev)
+    tws = torch.empty(int(xgs.lib.xgs_tracking_loss_workspace(out.shape[1], out.shape[2])), dtype=torch.uint8,
+                      device=dev)
+    d_pose = torch.empty(6, device=dev)
+    prune = torch.empty(g.n, dtype=torch.uint8, device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    S = torch.randint(-1, 100, (480, 640), dtype=torch.int32, device=dev)
+    Phi = torch.randn(100, 512, device=dev)
+    Gr = torch.empty((512, 480, 640), device=dev)
+    Vr = torch.empty((480, 640), dtype=torch.uint8, device=dev)
+    names = ["tracking_loss", "render_bwd", "pose_grad", "occluder_mask", "region_targets"]
+
+    def run(evs):
+        evs[0].record(stream)
+        xgs.xgs_tracking_loss(out, image, depth, 0.05, d_out=d_out, loss=loss, workspace=tws)
+        evs[1].record(stream)
+        xgs.xgs_render_bwd(g, p, b, cam, d_out, fT, nl, grads=grads, workspace=bwd_ws)
+        evs[2].record(stream)
+        xgs.xgs_pose_grad(g, p, cam, bwd_ws, d_pose=d_pose)
+        evs[3].record(stream)
+        xgs.xgs_occluder_mask(p, g.n, depth, 0.1, prune=prune, count=cnt)
+        evs[4].record(stream)
+        xgs.xgs_region_targets(S, Phi, G=Gr, V=Vr)
+        evs[5].record(stream)
+
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+    for _ in range(3):
+        run(mk())
+    torch.cuda.synchronize()
+    evs_all = [mk() for _ in range(reps)]
+    for evs in evs_all:
+        run(evs)
+    torch.cuda.synchronize()
+    ms = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs_all])) for i, n in enumerate(names)}
+    reg_bytes = 512 * 480 * 640 * 4 + 480 * 640 * (4 + 1)
+    return {"ms": {k: round(v, 4) for k, v in ms.items()},
+            "tracking_step_ms": round(ms["tracking_loss"] + ms["render_bwd"] + ms["pose_grad"], 4),
+            "pruned": int(cnt.item()), "region_targets_GBps": round(reg_bytes / (ms["region_targets"] * 1e-3) / 1e9, 1),
+            "workload": "1M room 1200x680 (tracking: L1 photo + 0.05 L1 depth, pose gradient; occluders vs a depth "
+                        "map 1% behind the render), region targets 640x480 D=512 R=100"}
 
 
 def serving(xgs, synth, dev, n_requests):

@@ -320,6 +320,16 @@ xgs_status xgs_vq_candidates(int64_t N, int32_t D, int32_t K, void* ws, size_t w
 xgs_status xgs_vq_rescore(const float* X, int64_t N, int32_t D, const float* E, int32_t K,
                           int32_t* idx, float* dist, void* ws, size_t ws_bytes, xgs_stream_t stream);
 
+/* App. C, Eq. (confidence_score): the BF16 form of xgs_vq_assign that also
+ * returns conf [N] = max_k p_nk, p_nk = softmax_k(-|x_n - e_k| / tau), from
+ * the unsquared distances of the bf16 operands (one log-sum-exp over every
+ * codeword, fused in the MFMA sweep; the assignment itself is unchanged).
+ * Same arguments and workspace as xgs_vq_assign with precision BF16. */
+xgs_status xgs_vq_assign_conf(const float* X, int64_t N, int32_t D, const float* E,
+                              const uint16_t* E_bf16, const float* e_norm2, int32_t K, float tau,
+                              int32_t* idx, float* dist, float* conf, void* ws, size_t ws_bytes,
+                              xgs_stream_t stream);
+
 /* --------------------------------------------------------- a7: EMA update
  * Eq. (ema_update): c_l = #{a_n = l}, s_l = sum_{a_n = l} x_n,
  * N <- decay N + (1-decay) c, M <- decay M + (1-decay) s, then
@@ -333,6 +343,22 @@ xgs_status xgs_vq_ema_update(const float* X, const int32_t* idx, int64_t N, int3
                              float* N_ema, float* M_ema, float* E, uint16_t* E_bf16,
                              float* e_norm2, float* counts, float decay, float eps, int32_t mode,
                              void* ws, size_t ws_bytes, xgs_stream_t stream);
+
+/* App. C: the EMA step of xgs_vq_ema_update with the confidence mask
+ * (Eq. (mask_confidence): only rows with conf[n] >= gamma update c and s;
+ * conf == NULL keeps every row) and the dead-code reset (Eq. (dead_code)):
+ * after the decay step every codeword with N_k < delta takes M_k <- reservoir
+ * row (offset + j) mod R for the j-th such codeword in index order and
+ * N_k <- 1 + eps (delta <= 0: no reset); E, E_bf16, e_norm2 are then
+ * recomputed from N and M.  reservoir [R][D] FP32 (recent features);
+ * *n_dead (device int32, may be NULL) = number reset.  A warm start is this
+ * call with decay 0.  ws: xgs_vq_ema_workspace(N, D, K) bytes. */
+xgs_status xgs_vq_ema_update_robust(const float* X, const int32_t* idx, const float* conf, float gamma,
+                                    int64_t N, int32_t D, int32_t K, float* N_ema, float* M_ema, float* E,
+                                    uint16_t* E_bf16, float* e_norm2, float* counts, float decay, float eps,
+                                    int32_t mode, float delta, const float* reservoir, int32_t R,
+                                    int64_t offset, int32_t* n_dead, void* ws, size_t ws_bytes,
+                                    xgs_stream_t stream);
 
 #ifdef __cplusplus
 }

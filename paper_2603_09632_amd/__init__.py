@@ -36,7 +36,7 @@ __all__ = [
     "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_stage", "xgs_vq_candidates", "xgs_vq_rescore",
     "vq_assign_workspace", "xgs_vq_ema_update", "xgs_semantic_softmax", "xgs_semantic_softmax_bwd",
     "xgs_semantic_loss", "semantic_step", "xgs_pose_grad", "xgs_tracking_loss", "tracking_step", "xgs_region_targets",
-    "xgs_occluder_mask", "render",
+    "xgs_occluder_mask", "xgs_vq_assign_conf", "xgs_vq_ema_update_robust", "render",
 ]
 
 
@@ -395,6 +395,40 @@ def semantic_step(g: "Gaussians", p: "Projected", b: "Binning", cam, z: torch.Te
     grads = xgs_render_bwd(gw, p, b, cam, d_out, fT, nl, flags=BWD_FEATURES_ONLY, stream=stream)
     dz = xgs_semantic_softmax_bwd(w, grads.features, stream=stream)
     return loss, dz, out
+
+
+def xgs_vq_assign_conf(X: torch.Tensor, E: torch.Tensor, E_bf16, e_norm2, tau: float = 0.7, idx=None, dist=None,
+                       conf=None, workspace=None, stream=None):
+    N, D = X.shape
+    K = E.shape[0]
+    idx = idx if idx is not None else torch.empty(N, dtype=torch.int32, device=X.device)
+    dist = dist if dist is not None else torch.empty(N, dtype=torch.float32, device=X.device)
+    conf = conf if conf is not None else torch.empty(N, dtype=torch.float32, device=X.device)
+    if workspace is None:
+        workspace = vq_assign_workspace(N, D, K, VQ_BF16_RESCORE4, X.device)
+    check(lib.xgs_vq_assign_conf(_ptr(X), N, D, _ptr(E), _ptr(E_bf16), _ptr(e_norm2), K, float(tau), _ptr(idx),
+                                 _ptr(dist), _ptr(conf), _ptr(workspace), workspace.numel(), _stream(stream)),
+          "xgs_vq_assign_conf")
+    return idx, dist, conf
+
+
+def xgs_vq_ema_update_robust(X, idx, conf, gamma: float, N_ema, M_ema, E, E_bf16=None, e_norm2=None,
+                             decay: float = 0.96, eps: float = 1e-5, mode: int = EMA_PAPER, delta: float = 0.0,
+                             reservoir=None, offset: int = 0, counts=None, n_dead=None, workspace=None, stream=None):
+    N, D = X.shape
+    K = M_ema.shape[0]
+    counts = counts if counts is not None else torch.empty(K, dtype=torch.float32, device=X.device)
+    n_dead = n_dead if n_dead is not None else torch.empty(1, dtype=torch.int32, device=X.device)
+    need = int(lib.xgs_vq_ema_workspace(N, D, K))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
+    R = 0 if reservoir is None else reservoir.shape[0]
+    check(lib.xgs_vq_ema_update_robust(_ptr(X), _ptr(idx), _ptr(conf), float(gamma), N, D, K, _ptr(N_ema),
+                                       _ptr(M_ema), _ptr(E), _ptr(E_bf16), _ptr(e_norm2), _ptr(counts), float(decay),
+                                       float(eps), int(mode), float(delta), _ptr(reservoir), R, int(offset),
+                                       _ptr(n_dead), _ptr(workspace), workspace.numel(), _stream(stream)),
+          "xgs_vq_ema_update_robust")
+    return counts, n_dead
 
 
 def xgs_vq_ema_update(X, idx, N_ema, M_ema, E, E_bf16=None, e_norm2=None, decay: float = 0.99,

@@ -86,6 +86,12 @@ SIGNATURES = {
     "xgs_semantic_loss_workspace": (c_size_t, [c_int32, c_int32]),
     "xgs_semantic_loss": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p,
                                     c_float, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "xgs_vq_assign_conf": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_float,
+                                     c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "xgs_vq_ema_update_robust": (c_int32, [c_void_p, c_void_p, c_void_p, c_float, c_int64, c_int32, c_int32,
+                                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float,
+                                           c_float, c_int32, c_float, c_void_p, c_int32, c_int64, c_void_p,
+                                           c_void_p, c_size_t, c_void_p]),
     "xgs_vq_ema_workspace": (c_size_t, [c_int64, c_int32, c_int32]),
     "xgs_vq_ema_update": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p,
                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float,

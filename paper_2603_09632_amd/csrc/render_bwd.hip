@@ -475,13 +475,26 @@ __global__ void __launch_bounds__(256) pose_grad_kernel(
             (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-__global__ void __launch_bounds__(64) pose_total_kernel(const float* __restrict__ partial, int64_t nb,
-                                                       float* __restrict__ d_pose) {
-    const int k = threadIdx.x;
-    if (k >= 6) return;
-    float s = 0.f;
-    for (int64_t b = 0; b < nb; ++b) s += partial[(size_t)b * 6 + k];
-    d_pose[k] = s;
+// Thread j sums the partials of blocks j, j + 256, ... in order, then a
+// fixed tree combines the 256 sums: deterministic.
+__global__ void __launch_bounds__(256) pose_total_kernel(const float* __restrict__ partial, int64_t nb,
+                                                        float* __restrict__ d_pose) {
+    __shared__ float red[6][256];
+    const int t = threadIdx.x;
+    float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t b = t; b < nb; b += 256)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[k] += partial[(size_t)b * 6 + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[k][t] = s[k];
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (t < o)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) red[k][t] += red[k][t + o];
+        __syncthreads();
+    }
+    if (t < 6) d_pose[t] = red[t][0];
 }
 
 template <int CS, bool GEO, bool EXACT = true>
@@ -618,6 +631,6 @@ extern "C" xgs_status xgs_pose_grad(const xgs_gaussians* g, const xgs_projected*
     hipLaunchKernelGGL(pose_grad_kernel, dim3((unsigned)nb), dim3(256), 0, st, g->n, g->means, g->log_scales,
                        reinterpret_cast<const float4*>(g->quats), p->radius,
                        reinterpret_cast<const float4*>(p->splat), geo, cam_dev_b(*cam), partial);
-    hipLaunchKernelGGL(pose_total_kernel, dim3(1), dim3(64), 0, st, partial, (int64_t)nb, d_pose);
+    hipLaunchKernelGGL(pose_total_kernel, dim3(1), dim3(256), 0, st, partial, (int64_t)nb, d_pose);
     return check_launch("xgs_pose_grad");
 }

@@ -294,10 +294,16 @@ __global__ void __launch_bounds__(256) vq_eprep_kernel(const uint16_t* __restric
     }
 }
 
+// CONF: also the confidence of App. C, Eq. (confidence_score), from the same
+// accumulators: per row a running log-sum-exp (m, s) of v_k = -d_k / tau over
+// every codeword, d_k = sqrt(2 acc_k) the unsquared bf16 distance; merged over
+// the four lists of a row and written to lse[row][part].
+template <bool CONF>
 __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restrict__ Xa, int64_t N, int Dx,
                                                         const uint16_t* __restrict__ Ea, int K, int parts,
                                                         int tiles_part, int seq_bits,
-                                                        int2* __restrict__ cand) {
+                                                        int2* __restrict__ cand, float inv_tau,
+                                                        float2* __restrict__ lse) {
     __shared__ __align__(16) uint4 qbuf[Q_NBUF * Q_SLOTS];
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -386,6 +392,31 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
 #pragma unroll
         for (int q = 0; q < 4; ++q) top[jx][q] = 0x7FFFFFFF;
     const uint32_t keep = ~((1u << seq_bits) - 1u);
+    float lm[2] = {-INFINITY, -INFINITY}, ls[2] = {0.f, 0.f};
+    auto tile_lse = [&]() {
+#pragma unroll
+        for (int jx = 0; jx < 2; ++jx) {
+            float v[4][16];
+            float mt = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    v[i][r] = -__builtin_sqrtf(fmaxf(2.f * acc[i][jx][r], 0.f)) * inv_tau;
+                    mt = fmaxf(mt, v[i][r]);
+                }
+            const float mn = fmaxf(lm[jx], mt);
+            if (mn > -INFINITY) {  // a lane whose codewords are all padding adds nothing
+                float sum = ls[jx] * __expf(lm[jx] - mn);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) sum += __expf(v[i][r] - mn);
+                ls[jx] = sum;
+                lm[jx] = mn;
+            }
+        }
+    };
     auto tile_top4 = [&](int tl) {
 #pragma unroll
         for (int jx = 0; jx < 2; ++jx)
@@ -456,6 +487,7 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
             mfma_step(f1);
             b = bn;
         }
+        if constexpr (CONF) tile_lse();
         tile_top4(tl);
     }
     __syncthreads();
@@ -496,13 +528,32 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
 #pragma unroll
         for (int q = 0; q < 4; ++q) out[q] = make_int2(bk[q], bc[q]);
     }
+    if constexpr (CONF) {
+        // (m, s) of the four lists of each row, merged in list order
+        float2* ml = reinterpret_cast<float2*>(mc + Q_BM * 16);
+#pragma unroll
+        for (int jx = 0; jx < 2; ++jx) ml[(wm * 64 + 32 * jx + fr) * 4 + 2 * wn + hf] = make_float2(lm[jx], ls[jx]);
+        __syncthreads();
+        if (t < rows_here) {
+            float m = -INFINITY;
+            for (int e = 0; e < 4; ++e) m = fmaxf(m, ml[t * 4 + e].x);
+            float sum = 0.f;
+            for (int e = 0; e < 4; ++e) {
+                const float2 q = ml[t * 4 + e];
+                if (q.x > -INFINITY) sum += q.y * __expf(q.x - m);
+            }
+            lse[(r0 + t) * parts + p] = make_float2(m, sum);
+        }
+    }
 }
 
-template <bool V4>
+template <bool V4, bool CONF>
 __global__ void __launch_bounds__(256) vq_rescore_kernel(const float* __restrict__ X, int64_t N, int D,
                                                         const float* __restrict__ E, int K,
                                                         const int2* __restrict__ cand, int parts,
-                                                        int32_t* __restrict__ idx, float* __restrict__ dist) {
+                                                        int32_t* __restrict__ idx, float* __restrict__ dist,
+                                                        const float2* __restrict__ lse,
+                                                        float* __restrict__ conf) {
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= N) return;  // uniform per wave
@@ -562,12 +613,22 @@ __global__ void __launch_bounds__(256) vq_rescore_kernel(const float* __restrict
         idx[row] = bi;
         dist[row] = bd;
     }
+    if constexpr (CONF) {
+        // merge the parts' (m, s): conf = max_k p_k = 1 / sum_k exp(v_k - max v)
+        float2 q = lane < parts ? lse[row * parts + lane] : make_float2(-INFINITY, 0.f);
+        float m = q.x;
+        for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        float sum = q.x > -INFINITY ? q.y * __expf(q.x - m) : 0.f;
+        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (lane == 0) conf[row] = 1.f / sum;
+    }
 }
 
 struct VqWs {
     uint16_t* xa;
     uint16_t* ea;
     int2* cand;
+    float2* lse;
 };
 
 struct VqPlan {
@@ -600,12 +661,16 @@ static VqWs carve_vq(void* base, int64_t N, int D, const VqPlan& plan, size_t* b
     w.xa = c.take<uint16_t>((size_t)vq_np(n1) * dx);
     w.ea = c.take<uint16_t>((size_t)plan.parts * plan.tiles_part * Q_BN * dx);
     w.cand = c.take<int2>((size_t)n1 * plan.parts * 4);
+    w.lse = c.take<float2>((size_t)n1 * plan.parts);
     *bytes = c.total();
     return w;
 }
 
 // ------------------------------------------------------------------- EMA
+// Key = the assigned codeword; rows below the confidence threshold (App. C,
+// Eq. (mask_confidence)) go to the extra segment K, which no codeword reads.
 __global__ void ema_keys_kernel(const int32_t* __restrict__ idx, int64_t N, int K,
+                                const float* __restrict__ conf, float gamma,
                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                 int64_t* __restrict__ count) {
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -613,9 +678,49 @@ __global__ void ema_keys_kernel(const int32_t* __restrict__ idx, int64_t N, int 
     if (n >= N) return;
     int a = idx[n];
     a = a < 0 ? 0 : (a >= K ? K - 1 : a);
+    if (conf && !(conf[n] >= gamma)) a = K;
     keys[n] = (uint64_t)(uint32_t)a;
     vals[n] = (uint32_t)n;
 }
+
+// Dead codes (App. C, Eq. (dead_code)): N_k < delta after the EMA step.  One
+// workgroup ranks them in codeword order: rank[k] = j for the j-th dead code,
+// -1 otherwise; *n_dead = their number.
+__global__ void __launch_bounds__(1024) ema_dead_rank_kernel(const float* __restrict__ N_ema, int K, float delta,
+                                                            int32_t* __restrict__ rank, int32_t* __restrict__ n_dead) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (K + 1023) / 1024;
+    const int k0 = t * per, k1 = min(K, k0 + per);
+    int c = 0;
+    for (int k = k0; k < k1; ++k) c += N_ema[k] < delta;
+    part[t] = c;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan (Hillis-Steele)
+        const int v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int j = part[t] - c;
+    for (int k = k0; k < k1; ++k) rank[k] = N_ema[k] < delta ? j++ : -1;
+    if (t == 1023 && n_dead) *n_dead = part[1023];
+}
+
+// M_k <- reservoir[(offset + rank_k) mod R], N_k <- 1 + eps for dead codes.
+__global__ void __launch_bounds__(256) ema_dead_reinit_kernel(const int32_t* __restrict__ rank, int D,
+                                                             const float* __restrict__ reservoir, int R,
+                                                             int64_t offset, float eps, float* __restrict__ N_ema,
+                                                             float* __restrict__ M_ema) {
+    const int k = blockIdx.x;
+    const int j = rank[k];
+    if (j < 0) return;
+    const int64_t r = (offset + j) % R;
+    for (int d = threadIdx.x; d < D; d += 256) M_ema[(size_t)k * D + d] = reservoir[(size_t)r * D + d];
+    if (threadIdx.x == 0) N_ema[k] = 1.f + eps;
+}
+
+__global__ void ema_zero_i32_kernel(int32_t* __restrict__ p) { *p = 0; }
 
 // One workgroup per codeword: counts, row sums in ascending row order, EMA of
 // N and M.  Row ids are staged in LDS; each thread owns up to 4 columns and
@@ -732,6 +837,7 @@ struct EmaWs {
     uint32_t* ranges;
     int64_t* count;
     float* total;
+    int32_t* rank;
 };
 
 static EmaWs carve_ema(void* base, int64_t N, int K, size_t* bytes) {
@@ -743,9 +849,10 @@ static EmaWs carve_ema(void* base, int64_t N, int K, size_t* bytes) {
     w.keys_alt = c.take<uint64_t>(n1);
     w.vals_alt = c.take<uint32_t>(n1);
     w.hist = c.take<uint32_t>(radix_hist_words(n1, 64));
-    w.ranges = c.take<uint32_t>(2 * (size_t)(K > 0 ? K : 1));
+    w.ranges = c.take<uint32_t>(2 * (size_t)(K > 0 ? K + 1 : 2));
     w.count = c.take<int64_t>(1);
     w.total = c.take<float>(1);
+    w.rank = c.take<int32_t>((size_t)(K > 0 ? K : 1));
     *bytes = c.total();
     return w;
 }
@@ -826,8 +933,8 @@ extern "C" xgs_status xgs_vq_candidates(int64_t N, int32_t D, int32_t K, void* w
     if (xgs_status s = vq_bf16_setup("xgs_vq_candidates", N, D, K, ws, ws_bytes, &plan, &w)) return s;
     if (N == 0) return XGS_OK;
     const int64_t blocks = ((N + Q_BM - 1) / Q_BM + 7) / 8 * 8 * plan.parts;
-    hipLaunchKernelGGL(vq_gemm_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, w.xa, N,
-                       vq_dp(D) + Q_BK, w.ea, K, plan.parts, plan.tiles_part, plan.seq_bits, w.cand);
+    hipLaunchKernelGGL(vq_gemm_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, w.xa, N,
+                       vq_dp(D) + Q_BK, w.ea, K, plan.parts, plan.tiles_part, plan.seq_bits, w.cand, 0.f, nullptr);
     return check_launch("xgs_vq_candidates");
 }
 
@@ -842,12 +949,38 @@ extern "C" xgs_status xgs_vq_rescore(const float* X, int64_t N, int32_t D, const
     hipStream_t st = (hipStream_t)stream;
     const unsigned blocks = (unsigned)((N + 3) / 4);
     if (D % 4 == 0 && aligned(X, 16) && aligned(E, 16))
-        hipLaunchKernelGGL(vq_rescore_kernel<true>, dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand, plan.parts,
-                           idx, dist);
+        hipLaunchKernelGGL((vq_rescore_kernel<true, false>), dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand,
+                           plan.parts, idx, dist, nullptr, nullptr);
     else
-        hipLaunchKernelGGL(vq_rescore_kernel<false>, dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand,
-                           plan.parts, idx, dist);
+        hipLaunchKernelGGL((vq_rescore_kernel<false, false>), dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand,
+                           plan.parts, idx, dist, nullptr, nullptr);
     return check_launch("xgs_vq_rescore");
+}
+
+extern "C" xgs_status xgs_vq_assign_conf(const float* X, int64_t N, int32_t D, const float* E,
+                                         const uint16_t* E_bf16, const float* e_norm2, int32_t K, float tau,
+                                         int32_t* idx, float* dist, float* conf, void* ws, size_t ws_bytes,
+                                         xgs_stream_t stream) {
+    clear_error();
+    VqPlan plan;
+    VqWs w;
+    if (xgs_status s = vq_bf16_setup("xgs_vq_assign_conf", N, D, K, ws, ws_bytes, &plan, &w)) return s;
+    if (!(tau > 0.f)) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_assign_conf: tau must be positive");
+    if (N == 0) return XGS_OK;
+    if (!X || !E || !idx || !dist || !conf) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_assign_conf: null pointer");
+    if (xgs_status s = xgs_vq_stage(X, N, D, E_bf16, e_norm2, K, ws, ws_bytes, stream)) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t gb = ((N + Q_BM - 1) / Q_BM + 7) / 8 * 8 * plan.parts;
+    hipLaunchKernelGGL(vq_gemm_kernel<true>, dim3((unsigned)gb), dim3(256), 0, st, w.xa, N, vq_dp(D) + Q_BK, w.ea, K,
+                       plan.parts, plan.tiles_part, plan.seq_bits, w.cand, 1.f / tau, w.lse);
+    const unsigned blocks = (unsigned)((N + 3) / 4);
+    if (D % 4 == 0 && aligned(X, 16) && aligned(E, 16))
+        hipLaunchKernelGGL((vq_rescore_kernel<true, true>), dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand,
+                           plan.parts, idx, dist, w.lse, conf);
+    else
+        hipLaunchKernelGGL((vq_rescore_kernel<false, true>), dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand,
+                           plan.parts, idx, dist, w.lse, conf);
+    return check_launch("xgs_vq_assign_conf");
 }
 
 extern "C" xgs_status xgs_vq_assign(const float* X, int64_t N, int32_t D, const float* E,
@@ -880,33 +1013,36 @@ extern "C" size_t xgs_vq_ema_workspace(int64_t N, int32_t D, int32_t K) {
     return bytes;
 }
 
-extern "C" xgs_status xgs_vq_ema_update(const float* X, const int32_t* idx, int64_t N, int32_t D,
-                                        int32_t K, float* N_ema, float* M_ema, float* E,
-                                        uint16_t* E_bf16, float* e_norm2, float* counts, float decay,
-                                        float eps, int32_t mode, void* ws, size_t ws_bytes,
-                                        xgs_stream_t stream) {
-    clear_error();
-    if (N < 0 || D < 1 || K < 1) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_ema_update: bad sizes");
-    if (N >= ((int64_t)1 << 32)) return fail(XGS_ERR_UNSUPPORTED, "xgs_vq_ema_update: N must be below 2^32");
-    if (!(decay >= 0.f && decay < 1.f)) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_ema_update: decay must be in [0, 1)");
-    if (mode != XGS_EMA_PAPER && mode != XGS_EMA_LAPLACE)
-        return fail(XGS_ERR_INVALID_ARG, "xgs_vq_ema_update: unknown mode");
-    if ((N > 0 && (!X || !idx)) || !N_ema || !M_ema || !E)
-        return fail(XGS_ERR_INVALID_ARG, "xgs_vq_ema_update: null pointer");
+// One EMA step: optional confidence mask on the samples, optional dead-code
+// reinitialisation after the decay step.
+static xgs_status ema_impl(const char* who, const float* X, const int32_t* idx, const float* conf, float gamma,
+                           int64_t N, int32_t D, int32_t K, float* N_ema, float* M_ema, float* E,
+                           uint16_t* E_bf16, float* e_norm2, float* counts, float decay, float eps, int32_t mode,
+                           float delta, const float* reservoir, int32_t R, int64_t offset, int32_t* n_dead,
+                           void* ws, size_t ws_bytes, hipStream_t st) {
+    const std::string w_ = who;
+    if (N < 0 || D < 1 || K < 1) return fail(XGS_ERR_INVALID_ARG, w_ + ": bad sizes");
+    if (N >= ((int64_t)1 << 32)) return fail(XGS_ERR_UNSUPPORTED, w_ + ": N must be below 2^32");
+    if (K >= (1 << 30)) return fail(XGS_ERR_UNSUPPORTED, w_ + ": K too large");
+    if (!(decay >= 0.f && decay < 1.f)) return fail(XGS_ERR_INVALID_ARG, w_ + ": decay must be in [0, 1)");
+    if (mode != XGS_EMA_PAPER && mode != XGS_EMA_LAPLACE) return fail(XGS_ERR_INVALID_ARG, w_ + ": unknown mode");
+    if ((N > 0 && (!X || !idx)) || !N_ema || !M_ema || !E) return fail(XGS_ERR_INVALID_ARG, w_ + ": null pointer");
     if ((E_bf16 == nullptr) != (e_norm2 == nullptr))
-        return fail(XGS_ERR_INVALID_ARG, "xgs_vq_ema_update: E_bf16 and e_norm2 go together");
-    if (!aligned(ws, 256)) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_ema_update: workspace must be 256-byte aligned");
+        return fail(XGS_ERR_INVALID_ARG, w_ + ": E_bf16 and e_norm2 go together");
+    const bool dead_on = delta > 0.f;
+    if (dead_on && (!reservoir || R < 1 || offset < 0))
+        return fail(XGS_ERR_INVALID_ARG, w_ + ": dead-code reset needs a reservoir (R >= 1, offset >= 0)");
+    if (!aligned(ws, 256)) return fail(XGS_ERR_INVALID_ARG, w_ + ": workspace must be 256-byte aligned");
     size_t need = 0;
     EmaWs w = carve_ema(ws, N, K, &need);
-    if (!ws || ws_bytes < need) return fail(XGS_ERR_CAPACITY, "xgs_vq_ema_update: workspace too small");
-    hipStream_t st = (hipStream_t)stream;
+    if (!ws || ws_bytes < need) return fail(XGS_ERR_CAPACITY, w_ + ": workspace too small");
     xgs_status s;
-    if ((s = fill_u32(w.ranges, 2 * (int64_t)K, 0u, st))) return s;
+    if ((s = fill_u32(w.ranges, 2 * ((int64_t)K + 1), 0u, st))) return s;
     const int64_t n1 = N > 0 ? N : 1;
-    hipLaunchKernelGGL(ema_keys_kernel, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, idx, N, K, w.keys,
-                       w.vals, w.count);
-    if ((s = check_launch("xgs_vq_ema_update keys"))) return s;
-    const int bits = bits_for(K);
+    hipLaunchKernelGGL(ema_keys_kernel, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, idx, N, K, conf, gamma,
+                       w.keys, w.vals, w.count);
+    if ((s = check_launch(who))) return s;
+    const int bits = bits_for((int64_t)K + 1);
     if ((s = radix_sort(w.keys, w.vals, w.keys_alt, w.vals_alt, w.count, N, bits, w.hist, st))) return s;
     const bool even = radix_passes(bits) % 2 == 0;
     const uint64_t* sk = even ? w.keys : w.keys_alt;
@@ -914,8 +1050,37 @@ extern "C" xgs_status xgs_vq_ema_update(const float* X, const int32_t* idx, int6
     if ((s = segment_ranges(sk, w.count, N, 0, w.ranges, st))) return s;
     hipLaunchKernelGGL(ema_accum_kernel, dim3((unsigned)K), dim3(256), 0, st, X, D, sv, w.ranges, decay, N_ema,
                        M_ema, counts);
+    if (dead_on) {
+        hipLaunchKernelGGL(ema_dead_rank_kernel, dim3(1), dim3(1024), 0, st, N_ema, K, delta, w.rank, n_dead);
+        hipLaunchKernelGGL(ema_dead_reinit_kernel, dim3((unsigned)K), dim3(256), 0, st, w.rank, D, reservoir, R, offset,
+                           eps, N_ema, M_ema);
+    } else if (n_dead) {
+        hipLaunchKernelGGL(ema_zero_i32_kernel, dim3(1), dim3(1), 0, st, n_dead);
+    }
     hipLaunchKernelGGL(ema_total_kernel, dim3(1), dim3(256), 0, st, N_ema, K, w.total);
     hipLaunchKernelGGL(ema_finalize_kernel, dim3((unsigned)K), dim3(256), 0, st, N_ema, M_ema, K, D, eps, mode,
                        w.total, E, E_bf16, e_norm2);
-    return check_launch("xgs_vq_ema_update");
+    return check_launch(who);
+}
+
+extern "C" xgs_status xgs_vq_ema_update(const float* X, const int32_t* idx, int64_t N, int32_t D,
+                                        int32_t K, float* N_ema, float* M_ema, float* E,
+                                        uint16_t* E_bf16, float* e_norm2, float* counts, float decay,
+                                        float eps, int32_t mode, void* ws, size_t ws_bytes,
+                                        xgs_stream_t stream) {
+    clear_error();
+    return ema_impl("xgs_vq_ema_update", X, idx, nullptr, 0.f, N, D, K, N_ema, M_ema, E, E_bf16, e_norm2, counts,
+                    decay, eps, mode, 0.f, nullptr, 0, 0, nullptr, ws, ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" xgs_status xgs_vq_ema_update_robust(const float* X, const int32_t* idx, const float* conf, float gamma,
+                                               int64_t N, int32_t D, int32_t K, float* N_ema, float* M_ema,
+                                               float* E, uint16_t* E_bf16, float* e_norm2, float* counts,
+                                               float decay, float eps, int32_t mode, float delta,
+                                               const float* reservoir, int32_t R, int64_t offset,
+                                               int32_t* n_dead, void* ws, size_t ws_bytes, xgs_stream_t stream) {
+    clear_error();
+    return ema_impl("xgs_vq_ema_update_robust", X, idx, conf, gamma, N, D, K, N_ema, M_ema, E, E_bf16, e_norm2,
+                    counts, decay, eps, mode, delta, reservoir, R, offset, n_dead, ws, ws_bytes,
+                    (hipStream_t)stream);
 }
