@@ -149,12 +149,8 @@ __global__ void __launch_bounds__(256) vq_fp32_kernel(const float* __restrict__ 
 // and an insertion is four min/med3 operations with no branches.  The four
 // lists of a row are merged in LDS.  vq_rescore takes the best 4 over the
 // parts and picks the smallest direct FP32 distance.
-constexpr int Q_BM = 128;                      // rows per workgroup
 constexpr int Q_BN = 256;                      // codewords per tile
 constexpr int Q_BK = 32;                       // bf16 columns per chunk (64 bytes of a row)
-constexpr int Q_XSLOTS = Q_BM * 4;             // 16-byte slots of X per chunk buffer
-constexpr int Q_SLOTS = (Q_BM + Q_BN) * 4;     // slots per chunk buffer
-constexpr int Q_NBUF = 3;
 constexpr int Q_MAX_TILES = 16;                // tiles per part: position fits in 10 bits
 constexpr int Q_MAX_PARTS = 16;                // candidate lists per row in the rescore (x4 <= 64 lanes)
 constexpr int Q_MIN_PARTS = 4;
@@ -180,20 +176,6 @@ __device__ __forceinline__ i32x4_t lds_read16(uint32_t a) {
     i32x4_t v;
     asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"(a));
     return v;
-}
-
-// Waits until at most N LDS operations are outstanding (they complete in
-// order, so the reads of f, issued N operations ago or earlier, are done);
-// the operands tie the fragments to the wait.  N = -1 only ties them (an
-// earlier wait already covered the reads).
-template <int N>
-__device__ __forceinline__ void lds_wait(i32x4_t (&f)[6]) {
-    if constexpr (N == 0)
-        asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(f[0]), "+v"(f[1]), "+v"(f[2]), "+v"(f[3]), "+v"(f[4]), "+v"(f[5]));
-    else if constexpr (N == 6)
-        asm volatile("s_waitcnt lgkmcnt(6)" : "+v"(f[0]), "+v"(f[1]), "+v"(f[2]), "+v"(f[3]), "+v"(f[4]), "+v"(f[5]));
-    else
-        asm volatile("" : "+v"(f[0]), "+v"(f[1]), "+v"(f[2]), "+v"(f[3]), "+v"(f[4]), "+v"(f[5]));
 }
 
 __device__ __forceinline__ int med3i(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
@@ -229,7 +211,7 @@ __device__ __forceinline__ size_t tiled_at(int64_t row, int col, int B, int nkc)
 // One wavefront per row of the padded row count Np (rows >= N are zero);
 // Dp = D rounded up to 32, Dx = Dp + 32 columns.
 __global__ void __launch_bounds__(256) vq_xprep_kernel(const float* __restrict__ X, int64_t N, int64_t Np, int D,
-                                                      int Dp, int Dx, uint16_t* __restrict__ Xa) {
+                                                      int Dp, int Dx, int B, uint16_t* __restrict__ Xa) {
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= Np) return;
@@ -251,7 +233,7 @@ __global__ void __launch_bounds__(256) vq_xprep_kernel(const float* __restrict__
             p.x = ((uint32_t)h[0] | ((uint32_t)h[1] << 16)) ^ 0x80008000u;  // -x^ (sign flip is exact)
             p.y = ((uint32_t)h[2] | ((uint32_t)h[3] << 16)) ^ 0x80008000u;
         }
-        *reinterpret_cast<uint2*>(Xa + tiled_at(row, 4 * q, Q_BM, nkc)) = p;
+        *reinterpret_cast<uint2*>(Xa + tiled_at(row, 4 * q, B, nkc)) = p;
     }
     for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
     if (lane < 8) {
@@ -263,7 +245,7 @@ __global__ void __launch_bounds__(256) vq_xprep_kernel(const float* __restrict__
         uint2 p;
         p.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
         p.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
-        *reinterpret_cast<uint2*>(Xa + tiled_at(row, Dp + 4 * lane, Q_BM, nkc)) = p;
+        *reinterpret_cast<uint2*>(Xa + tiled_at(row, Dp + 4 * lane, B, nkc)) = p;
     }
 }
 
@@ -294,20 +276,74 @@ __global__ void __launch_bounds__(256) vq_eprep_kernel(const uint16_t* __restric
     }
 }
 
+// Tiling of the sweep: WMW x WNW wavefronts, each accumulating FX x FE
+// fragments of 32 x 32 (rows x codewords), NBUF chunk buffers in LDS, OCC
+// workgroups per CU.
+template <int WMW_, int WNW_, int FX_, int FE_, int NBUF_, int OCC_>
+struct GemmCfg {
+    static constexpr int WMW = WMW_, WNW = WNW_, FX = FX_, FE = FE_, NBUF = NBUF_, OCC = OCC_;
+    static constexpr int NW = WMW * WNW, THREADS = 64 * NW;
+    static constexpr int ROWS = WMW * FX * 32, COLS = WNW * FE * 32;
+    static constexpr int XSLOTS = ROWS * 4, SLOTS = (ROWS + COLS) * 4;
+    static constexpr int NX = ROWS / (16 * NW), NE = COLS / (16 * NW), NI = NX + NE;
+    static constexpr int NF = FX + FE;
+    static_assert(COLS == Q_BN && FE <= 4 && ROWS % (16 * NW) == 0 && COLS % (16 * NW) == 0, "tiling");
+};
+
+// 128 rows x 256 codewords per workgroup, 4 wavefronts of 64 x 128 (128
+// accumulators each), 3 chunk buffers (72 KB of LDS), two workgroups per CU.
+// Measured alternatives: 256 x 256 with 4 wavefronts of 128 x 128 and 4
+// buffers (one workgroup per CU) 14% slower; 256 x 256 with 8 wavefronts of
+// 64 x 128 and 4 buffers equal.
+using VqCfg = GemmCfg<2, 2, 2, 4, 3, 2>;
+
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(N) : "memory");
+}
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// Waits until at most N LDS operations are outstanding (they complete in
+// order, so reads issued N operations ago or earlier are done); the operands
+// tie the fragments to the wait.  N < 0 only ties them.
+template <int N, int NF>
+__device__ __forceinline__ void lds_waitn(i32x4_t (&f)[NF]) {
+    static_assert(NF == 6 || NF == 8, "fragment count");
+    if constexpr (NF == 6) {
+        if constexpr (N >= 0)
+            asm volatile("s_waitcnt lgkmcnt(%6)" : "+v"(f[0]), "+v"(f[1]), "+v"(f[2]), "+v"(f[3]), "+v"(f[4]), "+v"(f[5]) : "n"(N));
+        else
+            asm volatile("" : "+v"(f[0]), "+v"(f[1]), "+v"(f[2]), "+v"(f[3]), "+v"(f[4]), "+v"(f[5]));
+    } else {
+        if constexpr (N >= 0)
+            asm volatile("s_waitcnt lgkmcnt(%8)"
+                         : "+v"(f[0]), "+v"(f[1]), "+v"(f[2]), "+v"(f[3]), "+v"(f[4]), "+v"(f[5]), "+v"(f[6]), "+v"(f[7])
+                         : "n"(N));
+        else
+            asm volatile("" : "+v"(f[0]), "+v"(f[1]), "+v"(f[2]), "+v"(f[3]), "+v"(f[4]), "+v"(f[5]), "+v"(f[6]), "+v"(f[7]));
+    }
+}
+
 // CONF: also the confidence of App. C, Eq. (confidence_score), from the same
 // accumulators: per row a running log-sum-exp (m, s) of v_k = -d_k / tau over
 // every codeword, d_k = sqrt(2 acc_k) the unsquared bf16 distance; merged over
-// the four lists of a row and written to lse[row][part].
-template <bool CONF>
-__global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restrict__ Xa, int64_t N, int Dx,
-                                                        const uint16_t* __restrict__ Ea, int K, int parts,
-                                                        int tiles_part, int seq_bits,
-                                                        int2* __restrict__ cand, float inv_tau,
-                                                        float2* __restrict__ lse) {
-    __shared__ __align__(16) uint4 qbuf[Q_NBUF * Q_SLOTS];
+// the lists of a row and written to lse[row][part].
+template <class C, bool CONF>
+__global__ void __launch_bounds__(C::THREADS, C::OCC) vq_gemm_kernel(const uint16_t* __restrict__ Xa, int64_t N, int Dx,
+                                                                    const uint16_t* __restrict__ Ea, int K, int parts,
+                                                                    int tiles_part, int seq_bits,
+                                                                    int2* __restrict__ cand, float inv_tau,
+                                                                    float2* __restrict__ lse) {
+    constexpr int FX = C::FX, FE = C::FE, NF = C::NF, NBUF = C::NBUF, NI = C::NI;
+    constexpr int ROWS = C::ROWS, COLS = C::COLS, NW = C::NW;
+    constexpr int LISTS = 2 * C::WNW;
+    __shared__ __align__(16) uint4 qbuf[NBUF * C::SLOTS];
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int wm = w & 1, wn = w >> 1;
+    const int wm = w % C::WMW, wn = w / C::WMW;
     // Workgroups go round-robin to the 8 XCDs.  The parts of one row block
     // take the same XCD (and neighbouring dispatch slots), so its X chunks
     // are fetched into one L2 and served to all of them.
@@ -316,55 +352,50 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
     const int within = (int)(blk - grp * 8 * parts);
     const int p = within >> 3;
     const int64_t rb = grp * 8 + (within & 7);
-    const int64_t r0 = rb * Q_BM;
+    const int64_t r0 = rb * ROWS;
     if (r0 >= N) return;  // padding of the last group (whole workgroup)
-    const int c_part = p * tiles_part * Q_BN;
-    const int tiles = min(tiles_part, (K - c_part + Q_BN - 1) / Q_BN);
+    const int c_part = p * tiles_part * COLS;
+    const int tiles = min(tiles_part, (K - c_part + COLS - 1) / COLS);
     const int nkc = Dx / Q_BK;
     const int total = tiles * nkc;
-    const int rows_here = (int)min((int64_t)Q_BM, N - r0);
+    const int rows_here = (int)min((int64_t)ROWS, N - r0);
 
     // This wave's direct loads: instruction m fills slots 64 j .. 64 j + 63
-    // of a buffer, j = w + 4 m: X rows 16 j + lane / 4 for m = 0, 1, codeword
-    // rows 16 (w + 4 (m - 2)) + lane / 4 for m = 2..5; lane & 3 is the slot
-    // within the row, holding segment (lane & 3) ^ q_swz(row).  In the
-    // chunk-tiled operands those 16 rows are 1 KB of consecutive memory; the
-    // per-lane byte offsets are fixed and the chunk moves the (scalar) bases.
+    // of a buffer, j = w + NW m: X rows 16 j + lane / 4 for m < NX, codeword
+    // rows 16 (w + NW (m - NX)) + lane / 4 after; lane & 3 is the slot within
+    // the row, holding segment (lane & 3) ^ q_swz(row).  In the chunk-tiled
+    // operands those 16 rows are 1 KB of consecutive memory; the per-lane
+    // byte offsets are fixed and the chunk moves the (scalar) bases.
     const int lr = lane >> 2;
-    const char* xbase = reinterpret_cast<const char*>(Xa + (size_t)rb * nkc * Q_BM * Q_BK);
+    const char* xbase = reinterpret_cast<const char*>(Xa + (size_t)rb * nkc * ROWS * Q_BK);
     const char* ebase = reinterpret_cast<const char*>(Ea + (size_t)c_part * Dx);
-    uint32_t xoff[2], eoff[4];
+    uint32_t off[NI];
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        const int row = 16 * (w + 4 * m) + lr;
-        xoff[m] = (uint32_t)row * 64u + 16u * (uint32_t)((lane & 3) ^ q_swz(row));
-    }
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int row = 16 * (w + 4 * m) + lr;
-        eoff[m] = (uint32_t)row * 64u + 16u * (uint32_t)((lane & 3) ^ q_swz(row));
+    for (int m = 0; m < NI; ++m) {
+        const int row = 16 * (w + NW * (m < C::NX ? m : m - C::NX)) + lr;
+        off[m] = (uint32_t)row * 64u + 16u * (uint32_t)((lane & 3) ^ q_swz(row));
     }
     // next chunk to issue: tile, chunk within the tile, buffer
     int n_tl = 0, n_kc = 0, n_b = 0;
     auto issue = [&]() {
         const int tl = n_tl, kc = n_kc;
-        uint4* dst = qbuf + n_b * Q_SLOTS;
+        uint4* dst = qbuf + n_b * C::SLOTS;
         if (++n_kc == nkc) { n_kc = 0; ++n_tl; }
-        n_b = n_b == Q_NBUF - 1 ? 0 : n_b + 1;
-        const char* xb = xbase + (size_t)kc * (Q_BM * Q_BK * 2);
-        const char* eb = ebase + ((size_t)tl * nkc + kc) * (Q_BN * Q_BK * 2);
+        n_b = n_b == NBUF - 1 ? 0 : n_b + 1;
+        const char* xb = xbase + (size_t)kc * (ROWS * Q_BK * 2);
+        const char* eb = ebase + ((size_t)tl * nkc + kc) * (COLS * Q_BK * 2);
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
-            __builtin_amdgcn_global_load_lds((glb_void_t*)(xb + xoff[m]), (lds_void_t*)(dst + 64 * (w + 4 * m)), 16,
+        for (int m = 0; m < C::NX; ++m)
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(xb + off[m]), (lds_void_t*)(dst + 64 * (w + NW * m)), 16,
                                              0, 0);
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-            __builtin_amdgcn_global_load_lds((glb_void_t*)(eb + eoff[m]),
-                                             (lds_void_t*)(dst + Q_XSLOTS + 64 * (w + 4 * m)), 16, 0, 0);
+        for (int m = 0; m < C::NE; ++m)
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(eb + off[C::NX + m]),
+                                             (lds_void_t*)(dst + C::XSLOTS + 64 * (w + NW * m)), 16, 0, 0);
     };
 
-    // Fragment addresses: X fragment jx covers rows wm 64 + 32 jx + lane % 32,
-    // codeword fragment i rows wn 128 + 32 i + lane % 32; step ks reads
+    // Fragment addresses: X fragment jx covers rows wm 32 FX + 32 jx + lane % 32,
+    // codeword fragment i rows wn 32 FE + 32 i + lane % 32; step ks reads
     // segment 2 ks + lane / 32.  Rows 32 apart share the swizzle, so the
     // fragments of one step are 128 slots (2048 bytes) apart.
     const int fr = lane & 31, hf = lane >> 5;
@@ -372,46 +403,46 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
     uint32_t xa[2], ea[2];
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-        xa[ks] = qb0 + 16u * (uint32_t)q_slot(wm * 64 + fr, 2 * ks + hf);
-        ea[ks] = qb0 + 16u * (uint32_t)(Q_XSLOTS + q_slot(wn * 128 + fr, 2 * ks + hf));
+        xa[ks] = qb0 + 16u * (uint32_t)q_slot(wm * 32 * FX + fr, 2 * ks + hf);
+        ea[ks] = qb0 + 16u * (uint32_t)(C::XSLOTS + q_slot(wn * 32 * FE + fr, 2 * ks + hf));
     }
-    auto read_frags = [&](int b, int ks, i32x4_t (&f)[6]) {
-        const uint32_t o = (uint32_t)(b * Q_SLOTS * 16);
-        f[0] = lds_read16(xa[ks] + o);
-        f[1] = lds_read16(xa[ks] + o + 2048u);
+    auto read_frags = [&](int b, int ks, i32x4_t (&f)[NF]) {
+        const uint32_t o = (uint32_t)(b * C::SLOTS * 16);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) f[2 + i] = lds_read16(ea[ks] + o + 2048u * i);
+        for (int jx = 0; jx < FX; ++jx) f[jx] = lds_read16(xa[ks] + o + 2048u * jx);
+#pragma unroll
+        for (int i = 0; i < FE; ++i) f[FX + i] = lds_read16(ea[ks] + o + 2048u * i);
     };
 
     // accumulator r of codeword fragment i holds codeword
-    // tile base + wn 128 + 32 i + 8 (r / 4) + 4 hf + r % 4, row 32 jx + fr
-    f32x16_t acc[4][2];
-    int top[2][4];
+    // tile base + wn 32 FE + 32 i + 8 (r / 4) + 4 hf + r % 4, row 32 jx + fr
+    f32x16_t acc[FE][FX];
+    int top[FX][4];
 #pragma unroll
-    for (int jx = 0; jx < 2; ++jx)
+    for (int jx = 0; jx < FX; ++jx)
 #pragma unroll
         for (int q = 0; q < 4; ++q) top[jx][q] = 0x7FFFFFFF;
     const uint32_t keep = ~((1u << seq_bits) - 1u);
-    float lm[2] = {-INFINITY, -INFINITY}, ls[2] = {0.f, 0.f};
+    float lm[FX], ls[FX];
+#pragma unroll
+    for (int jx = 0; jx < FX; ++jx) { lm[jx] = -INFINITY; ls[jx] = 0.f; }
     auto tile_lse = [&]() {
 #pragma unroll
-        for (int jx = 0; jx < 2; ++jx) {
-            float v[4][16];
+        for (int jx = 0; jx < FX; ++jx) {
             float mt = -INFINITY;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < FE; ++i)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    v[i][r] = -__builtin_sqrtf(fmaxf(2.f * acc[i][jx][r], 0.f)) * inv_tau;
-                    mt = fmaxf(mt, v[i][r]);
-                }
+                for (int r = 0; r < 16; ++r)
+                    mt = fmaxf(mt, -__builtin_sqrtf(fmaxf(2.f * acc[i][jx][r], 0.f)) * inv_tau);
             const float mn = fmaxf(lm[jx], mt);
             if (mn > -INFINITY) {  // a lane whose codewords are all padding adds nothing
                 float sum = ls[jx] * __expf(lm[jx] - mn);
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < FE; ++i)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) sum += __expf(v[i][r] - mn);
+                    for (int r = 0; r < 16; ++r)
+                        sum += __expf(-__builtin_sqrtf(fmaxf(2.f * acc[i][jx][r], 0.f)) * inv_tau - mn);
                 ls[jx] = sum;
                 lm[jx] = mn;
             }
@@ -419,9 +450,9 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
     };
     auto tile_top4 = [&](int tl) {
 #pragma unroll
-        for (int jx = 0; jx < 2; ++jx)
+        for (int jx = 0; jx < FX; ++jx)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < FE; ++i) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int k = (int)((__float_as_uint(acc[i][jx][r]) & keep) |
@@ -431,59 +462,58 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
                     top[jx][1] = med3i(top[jx][0], top[jx][1], k);
                     top[jx][0] = min(top[jx][0], k);
                 }
+                // one fragment at a time: the scheduler would otherwise read
+                // every accumulator out at once
+                __builtin_amdgcn_sched_barrier(0);
+            }
     };
-    auto mfma_step = [&](const i32x4_t (&f)[6]) {
+    auto mfma_step = [&](const i32x4_t (&f)[NF]) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FE; ++i)
 #pragma unroll
-            for (int jx = 0; jx < 2; ++jx)
-                acc[i][jx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, f[2 + i]),
+            for (int jx = 0; jx < FX; ++jx)
+                acc[i][jx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, f[FX + i]),
                                                                     __builtin_bit_cast(bf16x8_t, f[jx]),
                                                                     acc[i][jx], 0, 0, 0);
     };
-    auto mfma_first = [&](const i32x4_t (&f)[6]) {
+    auto mfma_first = [&](const i32x4_t (&f)[NF]) {
         const f32x16_t z = {};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FE; ++i)
 #pragma unroll
-            for (int jx = 0; jx < 2; ++jx)
-                acc[i][jx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, f[2 + i]),
+            for (int jx = 0; jx < FX; ++jx)
+                acc[i][jx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, f[FX + i]),
                                                                     __builtin_bit_cast(bf16x8_t, f[jx]), z, 0,
                                                                     0, 0);
     };
 
-    // prologue: chunks 0 and 1 in flight, wait for chunk 0
-    issue();
-    if (total > 1) {
-        issue();
-        asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-    } else {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    }
+    // prologue: chunks 0 .. NBUF-2 in flight, wait for chunk 0
+    const int pre = min(total, NBUF - 1);
+    for (int c = 0; c < pre; ++c) issue();
+    if (pre == NBUF - 1) wait_vm<NI * (NBUF - 2)>();
+    else wait_vm<0>();
     __builtin_amdgcn_s_barrier();
-    if (total > 2) issue();
-    i32x4_t f0[6], f1[6];
+    if (total > NBUF - 1) issue();
+    i32x4_t f0[NF], f1[NF];
     read_frags(0, 0, f0);
     int g = 0, b = 0;
     for (int tl = 0; tl < tiles; ++tl) {
         for (int kc = 0; kc < nkc; ++kc, ++g) {
-            const int bn = b == Q_NBUF - 1 ? 0 : b + 1;
+            const int bn = b == NBUF - 1 ? 0 : b + 1;
             read_frags(b, 1, f1);
-            lds_wait<6>(f0);  // f0 was read before f1's six reads
+            lds_waitn<NF, NF>(f0);  // f0 was read before f1's reads
             if (kc == 0) mfma_first(f0);
             else mfma_step(f0);
-            // chunk g + 1 must have landed (own loads, then everyone's); chunk
-            // g + 2 may still be in flight.  All reads of buffer b are
-            // complete (lgkmcnt(0)), so after the barrier it can be refilled.
-            if (g + 2 < total) {
-                asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)" ::: "memory");
-            } else {
-                asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
-            }
+            // chunk g + 1 must have landed (own loads, then everyone's);
+            // chunks g + 2 .. g + NBUF - 1 may still be in flight.  All reads
+            // of buffer b are complete (lgkmcnt(0)), so after the barrier it
+            // can be refilled with chunk g + NBUF.
+            if (g + NBUF - 1 < total) wait_vm_lgkm0<NI * (NBUF - 2)>();
+            else wait_vm_lgkm0<0>();
             __builtin_amdgcn_s_barrier();
-            if (g + 3 < total) issue();
+            if (g + NBUF < total) issue();
             if (g + 1 < total) read_frags(bn, 0, f0);
-            lds_wait<-1>(f1);  // complete since the lgkmcnt(0) above
+            lds_waitn<-1, NF>(f1);  // complete since the lgkmcnt(0) above
             mfma_step(f1);
             b = bn;
         }
@@ -492,29 +522,29 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
     }
     __syncthreads();
 
-    // merge: row (0..127) x 4 lists (wn, hf) x 4 candidates
+    // merge: row x LISTS lists (wn, hf) x 4 candidates
     int2* mc = reinterpret_cast<int2*>(qbuf);
     const uint32_t pos_mask = (1u << seq_bits) - 1u;
 #pragma unroll
-    for (int jx = 0; jx < 2; ++jx) {
-        const int row = wm * 64 + 32 * jx + fr;
+    for (int jx = 0; jx < FX; ++jx) {
+        const int row = wm * 32 * FX + 32 * jx + fr;
         const int list = 2 * wn + hf;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int k = top[jx][q];
             const uint32_t s = (uint32_t)k & pos_mask;
-            const int c = c_part + (int)(s >> 6) * Q_BN + wn * 128 + 32 * (int)((s >> 4) & 3) +
+            const int c = c_part + (int)(s >> 6) * COLS + wn * 32 * FE + 32 * (int)((s >> 4) & 3) +
                           8 * (int)((s >> 2) & 3) + 4 * hf + (int)(s & 3);
             const bool ok = k != 0x7FFFFFFF && c < K;
-            mc[row * 16 + list * 4 + q] = make_int2(ok ? (int)((uint32_t)k & keep) : 0x7FFFFFFF, ok ? c : -1);
+            mc[(row * LISTS + list) * 4 + q] = make_int2(ok ? (int)((uint32_t)k & keep) : 0x7FFFFFFF, ok ? c : -1);
         }
     }
     __syncthreads();
-    if (t < rows_here) {
+    for (int row = t; row < rows_here; row += C::THREADS) {
         int bk[4] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
         int bc[4] = {-1, -1, -1, -1};
-        for (int e = 0; e < 16; ++e) {
-            const int2 v = mc[t * 16 + e];
+        for (int e = 0; e < LISTS * 4; ++e) {
+            const int2 v = mc[row * LISTS * 4 + e];
             int k = v.x, c = v.y;
             // carry the entry up the sorted list (static indices: registers)
 #pragma unroll
@@ -524,25 +554,26 @@ __global__ void __launch_bounds__(256, 2) vq_gemm_kernel(const uint16_t* __restr
                     bk[q] = k; bc[q] = c; k = tk; c = tc;
                 }
         }
-        int2* out = cand + ((r0 + t) * parts + p) * 4;
+        int2* out = cand + ((r0 + row) * parts + p) * 4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) out[q] = make_int2(bk[q], bc[q]);
     }
     if constexpr (CONF) {
-        // (m, s) of the four lists of each row, merged in list order
-        float2* ml = reinterpret_cast<float2*>(mc + Q_BM * 16);
+        // (m, s) of the lists of each row, merged in list order
+        float2* ml = reinterpret_cast<float2*>(mc + ROWS * LISTS * 4);
 #pragma unroll
-        for (int jx = 0; jx < 2; ++jx) ml[(wm * 64 + 32 * jx + fr) * 4 + 2 * wn + hf] = make_float2(lm[jx], ls[jx]);
+        for (int jx = 0; jx < FX; ++jx)
+            ml[(wm * 32 * FX + 32 * jx + fr) * LISTS + 2 * wn + hf] = make_float2(lm[jx], ls[jx]);
         __syncthreads();
-        if (t < rows_here) {
+        for (int row = t; row < rows_here; row += C::THREADS) {
             float m = -INFINITY;
-            for (int e = 0; e < 4; ++e) m = fmaxf(m, ml[t * 4 + e].x);
+            for (int e = 0; e < LISTS; ++e) m = fmaxf(m, ml[row * LISTS + e].x);
             float sum = 0.f;
-            for (int e = 0; e < 4; ++e) {
-                const float2 q = ml[t * 4 + e];
+            for (int e = 0; e < LISTS; ++e) {
+                const float2 q = ml[row * LISTS + e];
                 if (q.x > -INFINITY) sum += q.y * __expf(q.x - m);
             }
-            lse[(r0 + t) * parts + p] = make_float2(m, sum);
+            lse[(r0 + row) * parts + p] = make_float2(m, sum);
         }
     }
 }
@@ -651,7 +682,7 @@ static VqPlan vq_plan(int K) {
 }
 
 static int vq_dp(int D) { return (D + Q_BK - 1) / Q_BK * Q_BK; }
-static int64_t vq_np(int64_t N) { return (N + Q_BM - 1) / Q_BM * Q_BM; }
+static int64_t vq_np(int64_t N) { return (N + VqCfg::ROWS - 1) / VqCfg::ROWS * VqCfg::ROWS; }
 
 static VqWs carve_vq(void* base, int64_t N, int D, const VqPlan& plan, size_t* bytes) {
     Carve c(base);
@@ -893,9 +924,10 @@ static xgs_status vq_bf16_setup(const char* who, int64_t N, int32_t D, int32_t K
     *plan = vq_plan(K);
     if (plan->parts > Q_MAX_PARTS) return fail(XGS_ERR_UNSUPPORTED, std::string(who) + ": K above 65536");
     const int64_t dx = vq_dp(D) + Q_BK;
-    if ((int64_t)plan->parts * plan->tiles_part * Q_BN * dx >= ((int64_t)1 << 31) || Q_BM * dx >= ((int64_t)1 << 30))
+    if ((int64_t)plan->parts * plan->tiles_part * Q_BN * dx >= ((int64_t)1 << 31) ||
+        (int64_t)VqCfg::ROWS * dx >= ((int64_t)1 << 30))
         return fail(XGS_ERR_UNSUPPORTED, std::string(who) + ": codebook above 2^31 bf16 elements");
-    if (((N + Q_BM - 1) / Q_BM + 7) / 8 * 8 * plan->parts >= ((int64_t)1 << 31))
+    if (((N + VqCfg::ROWS - 1) / VqCfg::ROWS + 7) / 8 * 8 * plan->parts >= ((int64_t)1 << 31))
         return fail(XGS_ERR_UNSUPPORTED, std::string(who) + ": N too large");
     if (!aligned(ws, 256)) return fail(XGS_ERR_INVALID_ARG, std::string(who) + ": workspace must be 256-byte aligned");
     size_t need = 0;
@@ -919,7 +951,7 @@ extern "C" xgs_status xgs_vq_stage(const float* X, int64_t N, int32_t D, const u
     const int Kp = plan.parts * plan.tiles_part * Q_BN;
     if (N > 0)
         hipLaunchKernelGGL(vq_xprep_kernel, dim3((unsigned)((vq_np(N) + 3) / 4)), dim3(256), 0, st, X, N, vq_np(N), D, Dp,
-                           Dx, w.xa);
+                           Dx, VqCfg::ROWS, w.xa);
     hipLaunchKernelGGL(vq_eprep_kernel, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, st, E_bf16, e_norm2, K, D, Kp,
                        Dp, Dx, w.ea);
     return check_launch("xgs_vq_stage");
@@ -932,8 +964,8 @@ extern "C" xgs_status xgs_vq_candidates(int64_t N, int32_t D, int32_t K, void* w
     VqWs w;
     if (xgs_status s = vq_bf16_setup("xgs_vq_candidates", N, D, K, ws, ws_bytes, &plan, &w)) return s;
     if (N == 0) return XGS_OK;
-    const int64_t blocks = ((N + Q_BM - 1) / Q_BM + 7) / 8 * 8 * plan.parts;
-    hipLaunchKernelGGL(vq_gemm_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, w.xa, N,
+    const int64_t blocks = ((N + VqCfg::ROWS - 1) / VqCfg::ROWS + 7) / 8 * 8 * plan.parts;
+    hipLaunchKernelGGL((vq_gemm_kernel<VqCfg, false>), dim3((unsigned)blocks), dim3(VqCfg::THREADS), 0, (hipStream_t)stream, w.xa, N,
                        vq_dp(D) + Q_BK, w.ea, K, plan.parts, plan.tiles_part, plan.seq_bits, w.cand, 0.f, nullptr);
     return check_launch("xgs_vq_candidates");
 }
@@ -970,8 +1002,8 @@ extern "C" xgs_status xgs_vq_assign_conf(const float* X, int64_t N, int32_t D, c
     if (!X || !E || !idx || !dist || !conf) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_assign_conf: null pointer");
     if (xgs_status s = xgs_vq_stage(X, N, D, E_bf16, e_norm2, K, ws, ws_bytes, stream)) return s;
     hipStream_t st = (hipStream_t)stream;
-    const int64_t gb = ((N + Q_BM - 1) / Q_BM + 7) / 8 * 8 * plan.parts;
-    hipLaunchKernelGGL(vq_gemm_kernel<true>, dim3((unsigned)gb), dim3(256), 0, st, w.xa, N, vq_dp(D) + Q_BK, w.ea, K,
+    const int64_t gb = ((N + VqCfg::ROWS - 1) / VqCfg::ROWS + 7) / 8 * 8 * plan.parts;
+    hipLaunchKernelGGL((vq_gemm_kernel<VqCfg, true>), dim3((unsigned)gb), dim3(VqCfg::THREADS), 0, st, w.xa, N, vq_dp(D) + Q_BK, w.ea, K,
                        plan.parts, plan.tiles_part, plan.seq_bits, w.cand, 1.f / tau, w.lse);
     const unsigned blocks = (unsigned)((N + 3) / 4);
     if (D % 4 == 0 && aligned(X, 16) && aligned(E, 16))
