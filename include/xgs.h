@@ -125,7 +125,12 @@ typedef struct xgs_projected {
  *   num_instances: device int64 = number of valid keys M;
  *   status: device int32, 0 = ok, 1 = the instances exceeded max_instances;
  *     then num_instances = 0 and every range is empty (nothing is rendered),
- *     and the caller retries with larger buffers. */
+ *     and the caller retries with larger buffers;
+ *   tile_order [num_tiles] (may be NULL): the order in which the compositing
+ *     kernels take the tiles, written by xgs_tile_sort: descending list
+ *     length in buckets of 16 instances, ties by tile id (identity above
+ *     16384 tiles).  NULL: tiles in id order.  Any permutation gives the same
+ *     images and gradients up to the order of the gradient atomics. */
 typedef struct xgs_binning {
     uint64_t* keys;
     uint32_t* vals;
@@ -133,6 +138,7 @@ typedef struct xgs_binning {
     int64_t* num_instances;
     int32_t* status;
     int64_t max_instances;
+    uint32_t* tile_order;
 } xgs_binning;
 
 /* ------------------------------------------------------------------ info */

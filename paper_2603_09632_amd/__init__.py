@@ -151,12 +151,14 @@ class Binning:
     status: torch.Tensor         # [1] int32
     workspace: torch.Tensor      # u8
     max_instances: int
+    tile_order: Optional[torch.Tensor] = None  # [tiles] u32 (as int32); None: id order
 
     def struct(self) -> XgsBinning:
         s = XgsBinning()
         s.keys, s.vals, s.ranges, s.num_instances, s.status = (
             _ptr(self.keys), _ptr(self.vals), _ptr(self.ranges), _ptr(self.num_instances), _ptr(self.status))
         s.max_instances = int(self.max_instances)
+        s.tile_order = _ptr(self.tile_order)
         return s
 
 
@@ -187,7 +189,8 @@ def alloc_binning(n: int, max_instances: int, cam, device=None) -> Binning:
     return Binning(torch.empty(cap, dtype=torch.int64, device=d), torch.empty(cap, dtype=torch.int32, device=d),
                    torch.empty((ty * tx, 2), dtype=torch.int32, device=d),
                    torch.zeros(1, dtype=torch.int64, device=d), torch.zeros(1, dtype=torch.int32, device=d),
-                   torch.empty(max(ws, 1), dtype=torch.uint8, device=d), cap)
+                   torch.empty(max(ws, 1), dtype=torch.uint8, device=d), cap,
+                   torch.empty(ty * tx, dtype=torch.int32, device=d))
 
 
 def xgs_tile_sort(p: Projected, cam, n: int, b: Binning, stream=None) -> Binning:

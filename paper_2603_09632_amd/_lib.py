@@ -42,7 +42,8 @@ class XgsProjected(ctypes.Structure):
 
 class XgsBinning(ctypes.Structure):
     _fields_ = [("keys", c_void_p), ("vals", c_void_p), ("ranges", c_void_p),
-                ("num_instances", c_void_p), ("status", c_void_p), ("max_instances", c_int64)]
+                ("num_instances", c_void_p), ("status", c_void_p), ("max_instances", c_int64),
+                ("tile_order", c_void_p)]
 
 
 SIGNATURES = {

@@ -36,20 +36,20 @@ class RenderFunction(torch.autograd.Function):
         ctx.max_instances = b.max_instances
         ctx.save_for_backward(g.means, g.log_scales, g.quats, g.opacity, g.colors, g.features, p.splat,
                               p.radius, p.tile_rect, p.tiles_touched, b.keys, b.vals, b.ranges,
-                              b.num_instances, b.status, final_T, n_last)
+                              b.num_instances, b.status, b.tile_order, final_T, n_last)
         ctx.mark_non_differentiable(final_T, n_last)
         return out, final_T, n_last
 
     @staticmethod
     def backward(ctx, d_out, _d_final_T, _d_n_last):
         (means, log_scales, quats, opacity, colors, features, splat, radius, tile_rect, touched, keys, vals,
-         ranges, num_inst, status, final_T, n_last) = ctx.saved_tensors
+         ranges, num_inst, status, tile_order, final_T, n_last) = ctx.saved_tensors
         if int(status.item()) != 0:
             raise XgsError("render: the instance buffers overflowed in the forward pass")
         g = Gaussians(means, log_scales, quats, opacity, colors, features)
         p = Projected(splat, radius, tile_rect, touched)
         b = Binning(keys, vals, ranges, num_inst, status, torch.empty(1, dtype=torch.uint8, device=means.device),
-                    ctx.max_instances)
+                    ctx.max_instances, tile_order)
         flags = BWD_FEATURES_ONLY if ctx.features_only else BWD_ALL
         gr = xgs_render_bwd(g, p, b, ctx.cam, d_out.contiguous(), final_T, n_last, flags=flags)
         if ctx.features_only:

@@ -594,7 +594,7 @@ extern "C" xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected
     float* geo = static_cast<float*>(ws);
     xgs_status s;
     if (g->c_sem > 0 && (s = fill_f32(gr->features, g->n * g->c_sem, 0.f, st))) return s;
-    TileGrid tg = tile_grid(*cam);
+    TileGrid tg = tile_grid(*cam, b->tile_order);
     if (geo_on) {
         if ((s = fill_f32(gr->colors, 3 * g->n, 0.f, st))) return s;
         if ((s = fill_f32(gr->opacity, g->n, 0.f, st))) return s;

@@ -10,16 +10,19 @@ namespace xgs {
 // workgroups go round-robin to the 8 XCDs; the mapping below puts the four
 // quadrants of a tile on the same XCD so that the tile's list and splat
 // records are fetched into one L2.
+// order: the tile processing order (slot -> tile id), nullptr for id order.
 struct TileGrid {
     int hs, ws, tx, ty, tiles;
     int s, oy, ox;
+    const uint32_t* order;
 };
 
-inline TileGrid tile_grid(const xgs_camera& cam) {
+inline TileGrid tile_grid(const xgs_camera& cam, const uint32_t* order = nullptr) {
     Grid g = grid_of(cam);
     TileGrid t;
     t.hs = g.hs; t.ws = g.ws; t.tx = g.tx; t.ty = g.ty; t.tiles = g.tx * g.ty;
     t.s = cam.stride; t.oy = cam.off_y; t.ox = cam.off_x;
+    t.order = order;
     return t;
 }
 
@@ -38,7 +41,10 @@ __device__ __forceinline__ QuadPix quad_pixel(const TileGrid& g) {
     const int xcd = b & 7, k = b >> 3;
     const int q = k & 3;
     QuadPix r;
-    r.tile = (k >> 2) * 8 + xcd;
+    // Slots go round-robin over the eight XCDs (the four quadrants of a slot
+    // share one XCD and its L2); the order table maps slot -> tile.
+    const int slot = (k >> 2) * 8 + xcd;
+    r.tile = (g.order && slot < g.tiles) ? (int)__builtin_amdgcn_readfirstlane((int)g.order[slot]) : slot;
     const int lane = threadIdx.x;
     const int tx = r.tile % g.tx, ty = r.tile / g.tx;
     r.n = tx * kTile + (q & 1) * 8 + (lane & 7);

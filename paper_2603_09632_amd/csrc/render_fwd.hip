@@ -164,7 +164,7 @@ extern "C" xgs_status xgs_render_fwd(const xgs_gaussians* g, const xgs_projected
         return fail(XGS_ERR_INVALID_ARG, "xgs_render_fwd: null Gaussian array");
     if (!b->ranges || !b->vals) return fail(XGS_ERR_INVALID_ARG, "xgs_render_fwd: null binning array");
     if (!aligned(p->splat, 16)) return fail(XGS_ERR_INVALID_ARG, "xgs_render_fwd: splat must be 16-byte aligned");
-    TileGrid tg = tile_grid(*cam);
+    TileGrid tg = tile_grid(*cam, b->tile_order);
     hipStream_t st = (hipStream_t)stream;
     switch (g->c_sem) {
 #define XGS_FWD_CASE(n) case n: launch_fwd<n>(g, p, b, tg, out, final_T, n_last, st); break;

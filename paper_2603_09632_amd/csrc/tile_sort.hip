@@ -57,6 +57,94 @@ static int tile_bits(int64_t tiles) {
     return b;
 }
 
+// Tile processing order for the compositing kernels: tiles by descending
+// list length (in buckets of 16 instances, capped at 255 buckets), ties by
+// tile index, so the longest lists are dispatched first and the short ones
+// fill the machine behind them.  One workgroup runs a stable counting sort on
+// the key 255 - bucket: each of the 16 wavefronts owns a contiguous range of
+// tile ids and walks it 64 tiles at a time; lanes with equal keys find each
+// other with eight ballots (one per key bit), so a lane's rank among equal
+// keys is a popcount and no atomics are needed.  The result is fully
+// determined.  Up to kOrderMax tiles; beyond that the order is the identity.
+constexpr int kOrderMax = 16384;
+constexpr int kOrderWaves = 16;
+
+__device__ __forceinline__ uint64_t same_key_lanes(uint32_t key, uint64_t valid) {
+    uint64_t m = valid;
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const bool on = (key >> bit) & 1u;
+        const uint64_t bl = __ballot(on);
+        m &= on ? bl : ~bl;
+    }
+    return m;
+}
+
+__global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __restrict__ ranges, int T,
+                                                         uint32_t* __restrict__ order) {
+    __shared__ uint32_t cnt[kOrderWaves][256];  // per wave and key: count, then next output slot
+    __shared__ uint32_t tot[256];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int i = t; i < kOrderWaves * 256; i += 1024) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int per = (T + kOrderWaves - 1) / kOrderWaves;
+    const int lo = min(T, w * per), hi = min(T, lo + per);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    auto key_of = [&](int i) {
+        const uint32_t len = ranges[2 * i + 1] - ranges[2 * i];
+        return 255u - min(len >> 4, 255u);
+    };
+    for (int i0 = lo; i0 < hi; i0 += 64) {
+        const int i = i0 + lane;
+        const bool ok = i < hi;
+        const uint32_t key = ok ? key_of(i) : 0u;
+        const uint64_t m = same_key_lanes(key, __ballot(ok));
+        if (ok && (m & lt) == 0) cnt[w][key] += (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    // exclusive prefix over keys of the totals, then over waves within a key
+    if (t < 256) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int v = 0; v < kOrderWaves; ++v) s += cnt[v][t];
+        tot[t] = s;
+    }
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        uint32_t v = 0;
+        if (t < 256 && t >= d) v = tot[t - d];
+        __syncthreads();
+        if (t < 256) tot[t] += v;
+        __syncthreads();
+    }
+    if (t < 256) {
+        uint32_t s = t > 0 ? tot[t - 1] : 0u;  // tiles with a smaller key
+#pragma unroll
+        for (int v = 0; v < kOrderWaves; ++v) {
+            const uint32_t c = cnt[v][t];
+            cnt[v][t] = s;
+            s += c;
+        }
+    }
+    __syncthreads();
+    for (int i0 = lo; i0 < hi; i0 += 64) {
+        const int i = i0 + lane;
+        const bool ok = i < hi;
+        const uint32_t key = ok ? key_of(i) : 0u;
+        const uint64_t m = same_key_lanes(key, __ballot(ok));
+        const uint32_t base = ok ? cnt[w][key] : 0u;
+        const uint32_t pos = base + (uint32_t)__popcll(m & lt);
+        if (ok && pos < (uint32_t)T) order[pos] = (uint32_t)i;
+        // every lane has read its base before the group leader advances it
+        if (ok && (m & lt) == 0) cnt[w][key] = base + (uint32_t)__popcll(m);
+    }
+}
+
+__global__ void __launch_bounds__(256) tile_order_identity_kernel(int64_t T, uint32_t* __restrict__ order) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < T) order[i] = (uint32_t)i;
+}
+
 }  // namespace xgs
 
 using namespace xgs;
@@ -108,5 +196,13 @@ extern "C" xgs_status xgs_tile_sort(const xgs_projected* p, const xgs_camera* ca
         if ((s = check_launch("xgs_tile_sort emit"))) return s;
     }
     if ((s = radix_sort(k0, v0, k1, v1, b->num_instances, cap, bits, w.hist, st))) return s;
-    return segment_ranges(b->keys, b->num_instances, cap, 32, b->ranges, st);
+    if ((s = segment_ranges(b->keys, b->num_instances, cap, 32, b->ranges, st))) return s;
+    if (b->tile_order) {
+        if (tiles <= kOrderMax)
+            hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, st, b->ranges, (int)tiles, b->tile_order);
+        else
+            hipLaunchKernelGGL(tile_order_identity_kernel, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st,
+                               tiles, b->tile_order);
+    }
+    return check_launch("xgs_tile_sort order");
 }

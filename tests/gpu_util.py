@@ -91,4 +91,5 @@ def binning_from_oracle(xgs, keys, vals, ranges, n, cam):
         b.vals[:m].copy_(torch.from_numpy(vals.view(np.int32)))
     b.ranges.copy_(torch.from_numpy(np.ascontiguousarray(ranges).view(np.int32)))
     b.num_instances.fill_(m)
+    b.tile_order = None  # tiles in id order (the sort kernel writes the table)
     return b

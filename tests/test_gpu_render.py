@@ -92,6 +92,16 @@ def check_sort(xgs, pr, cam, n, extra_cap=0):
     np.testing.assert_array_equal(np_(b.keys)[:m].view(np.uint64), keys)
     np.testing.assert_array_equal(np_(b.vals)[:m].view(np.uint32), vals)
     np.testing.assert_array_equal(np_(b.ranges).view(np.uint32), ranges)
+    # scheduling table: a permutation of the tiles, longest lists first in
+    # buckets of 16 instances, ties by tile id (identity above 16384 tiles)
+    r = np.asarray(ranges, np.int64).reshape(-1, 2)
+    T = len(r)
+    if T <= 16384:
+        bucket = np.minimum((r[:, 1] - r[:, 0]) >> 4, 255)
+        want = np.argsort(((255 - bucket) << 16) | np.arange(T), kind="stable")
+    else:
+        want = np.arange(T)
+    np.testing.assert_array_equal(np_(b.tile_order).view(np.uint32), want.astype(np.uint32))
     return m
 
 
@@ -247,6 +257,30 @@ def test_render_fwd_empty_scene(xgs):
     r = run_render(xgs, scene, synth.tiny_camera(), max_instances=1)
     assert not np_(r["out"]).any()
     assert (np_(r["final_T"]) == 1).all() and not np_(r["n_last"]).any()
+
+
+def test_render_tile_order_is_only_a_schedule(xgs, room300k):
+    """Compositing in the sorted (longest list first) tile order and in tile id
+    order gives bit-identical images; gradients differ only by the order of
+    their atomic sums."""
+    cam = room_cam()
+    r = run_render(xgs, room300k, cam)
+    b = r["b"]
+    order = np_(b.tile_order).view(np.uint32)
+    assert np.array_equal(np.sort(order), np.arange(len(order)))
+    ids = xgs.Binning(b.keys, b.vals, b.ranges, b.num_instances, b.status, b.workspace, b.max_instances, None)
+    out, fT, nl = xgs.xgs_render_fwd(r["g"], r["p"], ids, r["cam"])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(np_(out), np_(r["out"]))
+    np.testing.assert_array_equal(np_(fT), np_(r["final_T"]))
+    np.testing.assert_array_equal(np_(nl), np_(r["n_last"]))
+    hs, ws, _, _ = oracle.grid_info(cam)
+    g = torch.from_numpy(synth.upstream_grad(4 + room300k.c_sem, hs, ws, seed=9)).cuda()
+    a = xgs.xgs_render_bwd(r["g"], r["p"], b, r["cam"], g, r["final_T"], r["n_last"])
+    c = xgs.xgs_render_bwd(r["g"], r["p"], ids, r["cam"], g, r["final_T"], r["n_last"])
+    torch.cuda.synchronize()
+    for k in GROUPS:
+        assert rel_l2(np_(getattr(a, k)), np_(getattr(c, k))) < 1e-5, k
 
 
 # ------------------------------------------------------------------ a4
