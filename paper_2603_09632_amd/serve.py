@@ -87,8 +87,12 @@ class _BufferSet:
         self.graph: Optional[torch.cuda.CUDAGraph] = None
         self.nbytes = sum(t.numel() * t.element_size() for t in (
             self.viewmat_dev, self.proj.splat, self.proj.radius, self.proj.tile_rect, self.proj.tiles_touched,
-            self.binning.keys, self.binning.vals, self.binning.ranges, self.binning.workspace, self.out,
-            self.final_T, self.n_last))
+            self.binning.keys, self.binning.vals, self.binning.ranges, self.binning.workspace,
+            self.binning.tile_order, self.out, self.final_T, self.n_last))
+        # The fills above ran on this thread's current stream; the set is used
+        # on the (non-blocking) launch streams, which wait for this event first.
+        self.ready = torch.cuda.Event()
+        self.ready.record()
 
     def enqueue(self, g: Gaussians):
         """project -> sort -> render on the current stream (also the body that
@@ -216,7 +220,7 @@ class Server:
         hs, ws, ty, tx = grid_dims(camera(res.width, res.height, res.fx, res.fy, res.cx, res.cy))
         from . import lib
         ws_bytes = int(lib.xgs_tile_sort_workspace(g.n, cap, ty * tx))
-        return (64 + g.n * 48 + cap * 12 + ty * tx * 8 + 16 + ws_bytes + (4 + g.c_sem) * hs * ws * 4
+        return (64 + g.n * 48 + cap * 12 + ty * tx * 12 + 16 + ws_bytes + (4 + g.c_sem) * hs * ws * 4
                 + hs * ws * 8)
 
     def _launch(self, req: _Request, bs: _BufferSet):
@@ -225,6 +229,7 @@ class Server:
         self._rr += 1
         bs.viewmat_host.copy_(torch.from_numpy(req.viewmat))
         with torch.cuda.stream(s):
+            s.wait_event(bs.ready)
             bs.viewmat_dev.copy_(bs.viewmat_host, non_blocking=True)
             if self.use_graphs:
                 if bs.graph is None:
