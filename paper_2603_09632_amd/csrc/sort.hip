@@ -125,82 +125,92 @@ xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint
 }
 
 // ------------------------------------------------------------ radix sort
-// Per block: digit histogram of its 4096 keys, written digit-major
-// (hist[d * nb + b]); per digit: a running total over all blocks.
+// Per block: digit histogram of its kSortItems keys, written digit-major
+// (hist[d * nb + b]).
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t* __restrict__ keys,
                                                                  const int64_t* __restrict__ count,
                                                                  int shift, uint32_t mask,
-                                                                 uint32_t* __restrict__ hist,
-                                                                 uint32_t* __restrict__ totals) {
+                                                                 uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];
     const int64_t m = *count;
     const int64_t base = (int64_t)blockIdx.x * kSortItems;
     h[threadIdx.x] = 0;
     __syncthreads();
     if (base < m) {
-#pragma unroll 4
+#pragma unroll
         for (int r = 0; r < kSortRounds; ++r) {
             int64_t i = base + r * kSortThreads + threadIdx.x;
             if (i < m) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
         }
     }
     __syncthreads();
-    const uint32_t c = h[threadIdx.x];
-    hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = c;
-    if (c) atomicAdd(&totals[threadIdx.x], c);
+    hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// One workgroup per digit d: offset of d = sum of the totals of smaller
-// digits, then an exclusive scan of d's per-block counts (contiguous, read in
-// coalesced chunks of 256).
-__global__ void __launch_bounds__(256) radix_scan_kernel(uint32_t* __restrict__ hist,
-                                                        const uint32_t* __restrict__ totals, int64_t nb) {
-    __shared__ uint32_t sh[256];
-    __shared__ uint32_t carry;
-    const int d = blockIdx.x, t = threadIdx.x;
-    sh[t] = t < d ? totals[t] : 0u;
-    __syncthreads();
-    for (int o = 128; o >= 1; o >>= 1) {
-        if (t < o) sh[t] += sh[t + o];
-        __syncthreads();
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
     }
-    if (t == 0) carry = sh[0];
-    __syncthreads();
+    return v;
+}
+
+// One workgroup per digit d: exclusive scan of d's per-block counts in place
+// (the offset of block b among the keys with digit d), and totals[d].
+__global__ void __launch_bounds__(256) radix_scan_kernel(uint32_t* __restrict__ hist,
+                                                        uint32_t* __restrict__ totals, int64_t nb) {
+    __shared__ uint32_t ws[4];
+    const int d = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
     uint32_t* row = hist + (int64_t)d * nb;
+    uint32_t carry = 0;
     for (int64_t b0 = 0; b0 < nb; b0 += 256) {
         const int64_t i = b0 + t;
         const uint32_t v = i < nb ? row[i] : 0u;
-        sh[t] = v;
+        const uint32_t incl = wave_incl_scan(v, lane);
+        if (lane == 63) ws[w] = incl;
         __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {
-            const uint32_t x = t >= o ? sh[t - o] : 0u;
-            __syncthreads();
-            sh[t] += x;
-            __syncthreads();
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t x = ws[k];
+            pre += k < w ? x : 0u;
+            tot += x;
         }
-        const uint32_t c = carry;
-        if (i < nb) row[i] = c + sh[t] - v;
-        __syncthreads();
-        if (t == 255) carry = c + sh[255];
+        if (i < nb) row[i] = carry + pre + incl - v;
+        carry += tot;
         __syncthreads();
     }
+    if (t == 0) totals[d] = carry;
 }
 
-// Stable scatter.  Items are ranked in block order (round, wave, lane): a
-// lane's rank among equal digits in its wave comes from 8 ballots, the
-// per-wave counts are prefixed through LDS, and a running per-digit base
-// carries the order across rounds.
+// Stable scatter.  The block first turns the 256 digit totals into digit
+// bases (exclusive prefix) and adds its own offsets within each digit.  Items
+// are ranked in block order (round, wave, lane): a lane's rank among equal
+// digits in its wave comes from the digit's ballots, the per-wave counts are
+// prefixed through LDS, and a running per-digit base carries the order across
+// rounds.
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const int64_t* __restrict__ count, int shift, uint32_t mask,
-    int nbits, const uint32_t* __restrict__ hist) {
+    int nbits, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals) {
     __shared__ uint32_t goff[256];
     __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t ws[4];
     const int64_t m = *count;
     const int64_t base = (int64_t)blockIdx.x * kSortItems;
     if (base >= m) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    goff[t] = hist[(int64_t)t * gridDim.x + blockIdx.x];
+    {
+        const uint32_t tv = totals[t];
+        const uint32_t incl = wave_incl_scan(tv, lane);
+        if (lane == 63) ws[w] = incl;
+        __syncthreads();
+        uint32_t pre = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pre += k < w ? ws[k] : 0u;
+        goff[t] = pre + incl - tv + hist[(int64_t)t * gridDim.x + blockIdx.x];
+    }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int r = 0; r < kSortRounds; ++r) {
         int64_t i = base + r * kSortThreads + t;
@@ -246,19 +256,17 @@ xgs_status radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, co
     int64_t nb = sort_blocks(cap);
     if (nb == 0) return XGS_OK;
     int passes = radix_passes(key_bits);
-    uint32_t* totals = hist + 256 * nb;  // 256 per pass
-    xgs_status s = fill_u32(totals, 256 * (int64_t)passes, 0u, stream);
-    if (s) return s;
+    uint32_t* totals = hist + 256 * nb;
     uint64_t* ki = k0; uint32_t* vi = v0; uint64_t* ko = k1; uint32_t* vo = v1;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
         int nbits = key_bits - shift < 8 ? key_bits - shift : 8;
         uint32_t mask = (1u << nbits) - 1u;
         hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, ki,
-                           count, shift, mask, hist, totals + 256 * p);
-        hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(256), 0, stream, hist, totals + 256 * p, nb);
+                           count, shift, mask, hist);
+        hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(256), 0, stream, hist, totals, nb);
         hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream,
-                           ki, vi, ko, vo, count, shift, mask, nbits, hist);
+                           ki, vi, ko, vo, count, shift, mask, nbits, hist, totals);
         uint64_t* tk = ki; ki = ko; ko = tk;
         uint32_t* tv = vi; vi = vo; vo = tv;
     }
