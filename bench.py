@@ -419,6 +419,7 @@ def serving(xgs, synth, dev, n_requests):
     for frac, seed in ((0.5, 49), (0.8, 50)):
         qps = frac * sat
         log(f"serving: saturation {sat:.0f} frames/s, Poisson run at {frac:.0%} = {qps:.0f} req/s")
+        c0 = (srv.sets_created, srv.evictions, srv.graphs_captured, srv.overflows)
         t0 = time.perf_counter()
         futs = poisson_load(srv, mk(n_requests), qps, seed=seed)
         for f in futs:
@@ -426,9 +427,12 @@ def serving(xgs, synth, dev, n_requests):
         wall = time.perf_counter() - t0
         st = srv.stats()
         srv.completed.clear()
+        c1 = (srv.sets_created, srv.evictions, srv.graphs_captured, srv.overflows)
         points.append({"load": frac, "offered_qps": round(qps, 1),
                        "achieved_frames_per_s": round(n_requests / wall, 1), "p50_ms": round(st["p50_ms"], 3),
-                       "p99_ms": round(st["p99_ms"], 3)})
+                       "p99_ms": round(st["p99_ms"], 3), "p99_queued_ms": round(st["p99_queued_ms"], 3),
+                       **{k: b - a for k, a, b in zip(("sets_created", "evictions", "graphs_captured", "overflows"),
+                                                      c0, c1)}})
     peak = srv.peak_ledger_bytes / 2 ** 20
     overflows = srv.overflows
     srv.close()

@@ -11,10 +11,10 @@ Scratch lives in buffer sets (projection, binning, image) keyed by (scene,
 resolution) and pooled: a finished request returns its set to the pool, and
 the HBM ledger counts every set that exists.  When a new set would exceed the
 budget, free sets are evicted (least recently used); if none is free the
-request waits.  Each buffer set carries a HIP graph of project -> tile sort ->
-render forward, captured on first use; the pose enters through a 16-float
-device buffer (xgs_project_posed), so a replay serves any pose.  Replays go
-round-robin to a pool of streams.
+request waits.  A buffer set runs its first request eagerly and then carries a
+HIP graph of project -> tile sort -> render forward, captured on its second
+use; the pose enters through a 16-float device buffer (xgs_project_posed), so
+a replay serves any pose.  Replays go round-robin to a pool of streams.
 
 Results are independent of what else is in flight: every kernel of a request
 reads only that request's scene and buffers, per-tile order is deterministic
@@ -85,6 +85,7 @@ class _BufferSet:
         self.n_last = torch.empty((hs, ws), dtype=torch.int32, device=dev)
         self.status_host = torch.zeros(1, dtype=torch.int32).pin_memory()
         self.graph: Optional[torch.cuda.CUDAGraph] = None
+        self.uses = 0
         self.nbytes = sum(t.numel() * t.element_size() for t in (
             self.viewmat_dev, self.proj.splat, self.proj.radius, self.proj.tile_rect, self.proj.tiles_touched,
             self.binning.keys, self.binning.vals, self.binning.ranges, self.binning.workspace,
@@ -116,6 +117,7 @@ class Server:
         self.use_graphs = use_graphs
         self.near = near
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        self._side = torch.cuda.Stream(device=self.device)
         self._rr = 0
         self._pool: dict = collections.defaultdict(list)  # key -> free buffer sets
         self._lru: collections.OrderedDict = collections.OrderedDict()  # free sets, LRU order
@@ -131,6 +133,9 @@ class Server:
         self.completed: list[RenderResult] = []
         self.rejected = 0
         self.overflows = 0
+        self.sets_created = 0
+        self.evictions = 0
+        self.graphs_captured = 0
         self._thread = threading.Thread(target=self._loop, name="xgs-serve", daemon=True)
         self._thread.start()
 
@@ -140,9 +145,9 @@ class Server:
         pair has been measured this is a generous bound (4 instances per
         Gaussian, at least the tile count), used for admission; the first
         buffer set of a pair measures the instance count at its request's pose
-        and keeps 1.5x of it.  A later overflow is detected on the device, the
-        request is re-rendered eagerly at the exact size, the capacity grows
-        to 1.25x of what was needed and the undersized set is discarded."""
+        and keeps 1.5x of it.  A later overflow is detected on the device:
+        the capacity grows to 1.25x of what the request needed, the undersized
+        set is discarded and the request goes back to the head of the queue."""
         key = (scene, res)
         if key in self._capacity:
             return self._capacity[key]
@@ -155,8 +160,9 @@ class Server:
         if key not in self._capacity:
             g = self.scenes[scene]
             cam = camera(res.width, res.height, res.fx, res.fy, res.cx, res.cy, near=self.near)
-            s = self.streams[0]
-            with torch.cuda.stream(s):
+            # on the side stream: the host waits for this projection only,
+            # not for the replays queued on the launch streams
+            with torch.cuda.stream(self._side):
                 vm = torch.from_numpy(viewmat).to(self.device, non_blocking=False)
                 p = xgs_project_posed(g, cam, vm)
                 m = int(p.tiles_touched.to(torch.int64).sum().item())
@@ -186,9 +192,13 @@ class Server:
         lat = np.array([r.latency_s for r in self.completed]) * 1e3
         if len(lat) == 0:
             return {"completed": 0}
+        qd = np.array([r.queued_s for r in self.completed]) * 1e3
         return {"completed": len(lat), "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-                "peak_hbm_scratch_MB": self.peak_ledger_bytes / 2 ** 20, "budget_MB": self.budget / 2 ** 20}
+                "p50_queued_ms": float(np.percentile(qd, 50)), "p99_queued_ms": float(np.percentile(qd, 99)),
+                "peak_hbm_scratch_MB": self.peak_ledger_bytes / 2 ** 20, "budget_MB": self.budget / 2 ** 20,
+                "sets_created": self.sets_created, "evictions": self.evictions,
+                "graphs_captured": self.graphs_captured, "overflows": self.overflows}
 
     # ------------------------------------------------------------ internals
     def _acquire(self, scene: str, res: Resolution, viewmat: np.ndarray) -> Optional[_BufferSet]:
@@ -202,10 +212,12 @@ class Server:
             _, victim = self._lru.popitem(last=False)
             self._pool[victim.key].remove(victim)
             self.ledger_bytes -= victim.nbytes
+            self.evictions += 1
             del victim
         if self.ledger_bytes + need > self.budget:
             return None
         bs = _BufferSet(self, scene, res, self._measure_capacity(scene, res, viewmat))
+        self.sets_created += 1
         self.ledger_bytes += bs.nbytes
         self.peak_ledger_bytes = max(self.peak_ledger_bytes, self.ledger_bytes)
         return bs
@@ -231,16 +243,25 @@ class Server:
         with torch.cuda.stream(s):
             s.wait_event(bs.ready)
             bs.viewmat_dev.copy_(bs.viewmat_host, non_blocking=True)
-            if self.use_graphs:
+            if self.use_graphs and bs.uses > 0:
                 if bs.graph is None:
-                    bs.enqueue(g)  # eager warm-up before capture
+                    # A set is captured on its second use (a set evicted after
+                    # one request never pays for a capture).  The capture runs
+                    # on the launch stream itself: unlike the torch.cuda.graph
+                    # context it does not synchronise the device, so requests
+                    # on the other streams keep running.
                     graph = torch.cuda.CUDAGraph()
-                    with torch.cuda.graph(graph, stream=s, capture_error_mode="thread_local"):
+                    graph.capture_begin(capture_error_mode="thread_local")
+                    try:
                         bs.enqueue(g)
+                    finally:
+                        graph.capture_end()
                     bs.graph = graph
+                    self.graphs_captured += 1
                 bs.graph.replay()
             else:
                 bs.enqueue(g)
+            bs.uses += 1
             image = bs.out.clone()
             final_T = bs.final_T.clone()
             bs.status_host.copy_(bs.binning.status, non_blocking=True)
@@ -251,27 +272,23 @@ class Server:
     def _finish(self, item):
         req, bs, ev, image, final_T, t_launch = item
         if int(bs.status_host.item()) != 0:
-            # capacity overflow: render once more, eagerly, at the exact size
-            g = self.scenes[req.scene]
-            s = self.streams[0]
-            with torch.cuda.stream(s):
-                vm = torch.from_numpy(req.viewmat).to(self.device)
-                p = xgs_project_posed(g, bs.cam, vm)
-                m = int(p.tiles_touched.to(torch.int64).sum().item())
-                b = alloc_binning(g.n, m, bs.cam, self.device)
-                xgs_tile_sort(p, bs.cam, g.n, b)
-                image, final_T, _ = xgs_render_fwd(g, p, b, bs.cam)
-                self._capacity[bs.key] = max(self._capacity.get(bs.key, 0), int(m * 1.25) + 1024)
-                self.overflows += 1
-            s.synchronize()
-            # the set is too small for this pair: drop it instead of pooling it
+            # Capacity overflow.  The set still holds this request's
+            # projection: count the instances it needed (a small reduction on
+            # a side stream), grow the pair's capacity, drop the undersized
+            # set and put the request back at the head of the queue, so the
+            # loop never blocks on a re-render.
+            with torch.cuda.stream(self._side):
+                self._side.wait_event(ev)
+                m = int(bs.proj.tiles_touched.to(torch.int64).sum().item())
+            self._capacity[bs.key] = max(self._capacity.get(bs.key, 0), int(m * 1.25) + 1024)
+            self.overflows += 1
             self.ledger_bytes -= bs.nbytes
-            bs = None
+            self._pending.appendleft(req)
+            return
         t = time.perf_counter()
         res = RenderResult(image, final_T, t - req.t_arrival, t_launch - req.t_arrival)
         self.completed.append(res)
-        if bs is not None:
-            self._release(bs)
+        self._release(bs)
         req.future.set_result(res)
 
     def _loop(self):
