@@ -21,19 +21,51 @@ namespace xgs {
 // Geometry workspace row per Gaussian (8 floats).
 enum { GW_MX = 0, GW_MY = 1, GW_A = 2, GW_B = 3, GW_C = 4, GW_DEPTH = 5, GW_STRIDE = 8 };
 
-// One halving step of the wavefront reduce-scatter: N live values, partner
-// lane = lane ^ K.  The lower lane keeps the first half, the upper lane the
-// second; an odd leftover value is summed on both and owned by the lower.
+// One halving step of the wavefront reduce-scatter: N live values; step K
+// pairs every lane whose bit K is 0 ("lower") with a partner whose bit K is 1
+// and whose higher bits agree.  The lower lane keeps the first half of the
+// values, the upper lane the second; an odd leftover value is summed on both
+// and owned by the lower.  The exchanges stay in registers: K = 32 and 16 use
+// v_permlane32_swap / v_permlane16_swap (which swap the partner halves of two
+// registers, so one add finishes a pair), K = 8 .. 1 use DPP within rows of 16
+// (row_ror:8, row_half_mirror, quad_perm [3,2,1,0], quad_perm [1,0,3,2]; each
+// is an involution that flips bit K and keeps the bits above it).
+template <int K>
+__device__ __forceinline__ float rs_dpp(float v) {
+    constexpr int ctrl = K == 8 ? 0x128 : K == 4 ? 0x141 : K == 2 ? 0x1B : 0xB1;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, true));
+}
+
+template <int K>
+__device__ __forceinline__ float rs_swap_sum(float x, float y) {
+    static_assert(K == 32 || K == 16, "lane swaps are for the two upper steps");
+    uint32_t u = __float_as_uint(x), w = __float_as_uint(y);
+    if constexpr (K == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(u, w, false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(u, w, false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+}
+
 template <int N, int K>
 __device__ __forceinline__ void rs_step(float* a, bool lower) {
     constexpr int H = N / 2;
+    if constexpr (K >= 16) {
+        // lower lanes get value i summed over the pair, upper lanes value H + i
 #pragma unroll
-    for (int i = 0; i < H; ++i) {
-        const float send = lower ? a[H + i] : a[i];
-        const float keep = lower ? a[i] : a[H + i];
-        a[i] = keep + __shfl_xor(send, K, 64);
+        for (int i = 0; i < H; ++i) a[i] = rs_swap_sum<K>(a[i], a[H + i]);
+        if (N % 2) a[H] = rs_swap_sum<K>(a[2 * H], a[2 * H]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const float send = lower ? a[H + i] : a[i];
+            const float keep = lower ? a[i] : a[H + i];
+            a[i] = keep + rs_dpp<K>(send);
+        }
+        if (N % 2) a[H] = a[2 * H] + rs_dpp<K>(a[2 * H]);
     }
-    if (N % 2) a[H] = a[2 * H] + __shfl_xor(a[2 * H], K, 64);
 }
 
 template <int N, int K>
@@ -213,8 +245,9 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
 #pragma unroll
                     for (int v = 0; v < VG; ++v) a[v] = 0.f;
                     if (contrib) {
-                        const float om = 1.f - e.alpha;
-                        const float Tk = T / om;
+                        const float om = 1.f - e.alpha;  // >= 0.01
+                        const float rom = __builtin_amdgcn_rcpf(om);
+                        const float Tk = T * rom;
                         w = e.alpha * Tk;
                         if (GEO) {
                             const float4* cr = reinterpret_cast<const float4*>(chl + k * CHP);
@@ -227,7 +260,7 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
                                 if (4 * c4 + 2 < CH) sd += gch[4 * c4 + 2] * v.z;
                                 if (4 * c4 + 3 < CH) sd += gch[4 * c4 + 3] * v.w;
                             }
-                            const float dalpha = Tk * sd - S / om;
+                            const float dalpha = Tk * sd - S * rom;
                             const bool clamped = !(s1.y * e.G < kAlphaMax);
                             const float dq = clamped ? 0.f : dalpha * s1.y * e.G * -0.5f;
                             a[0] = clamped ? 0.f : dalpha * e.G;
