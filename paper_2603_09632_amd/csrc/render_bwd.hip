@@ -15,105 +15,12 @@
 // Sigma = (R S)(R S)^T, p = Rv mu + t (App. A).
 #include "render_common.h"
 #include "sort.h"
+#include "wave.h"
 
 namespace xgs {
 
 // Geometry workspace row per Gaussian (8 floats).
 enum { GW_MX = 0, GW_MY = 1, GW_A = 2, GW_B = 3, GW_C = 4, GW_DEPTH = 5, GW_STRIDE = 8 };
-
-// One halving step of the wavefront reduce-scatter: N live values; step K
-// pairs every lane whose bit K is 0 ("lower") with a partner whose bit K is 1
-// and whose higher bits agree.  The lower lane keeps the first half of the
-// values, the upper lane the second; an odd leftover value is summed on both
-// and owned by the lower.  The exchanges stay in registers: K = 32 and 16 use
-// v_permlane32_swap / v_permlane16_swap (which swap the partner halves of two
-// registers, so one add finishes a pair), K = 8 .. 1 use DPP within rows of 16
-// (row_ror:8, row_half_mirror, quad_perm [3,2,1,0], quad_perm [1,0,3,2]; each
-// is an involution that flips bit K and keeps the bits above it).
-template <int K>
-__device__ __forceinline__ float rs_dpp(float v) {
-    constexpr int ctrl = K == 8 ? 0x128 : K == 4 ? 0x141 : K == 2 ? 0x1B : 0xB1;
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, true));
-}
-
-template <int K>
-__device__ __forceinline__ float rs_swap_sum(float x, float y) {
-    static_assert(K == 32 || K == 16, "lane swaps are for the two upper steps");
-    uint32_t u = __float_as_uint(x), w = __float_as_uint(y);
-    if constexpr (K == 32) {
-        const auto r = __builtin_amdgcn_permlane32_swap(u, w, false, false);
-        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    } else {
-        const auto r = __builtin_amdgcn_permlane16_swap(u, w, false, false);
-        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    }
-}
-
-template <int N, int K>
-__device__ __forceinline__ void rs_step(float* a, bool lower) {
-    constexpr int H = N / 2;
-    if constexpr (K >= 16) {
-        // lower lanes get value i summed over the pair, upper lanes value H + i
-#pragma unroll
-        for (int i = 0; i < H; ++i) a[i] = rs_swap_sum<K>(a[i], a[H + i]);
-        if (N % 2) a[H] = rs_swap_sum<K>(a[2 * H], a[2 * H]);
-    } else {
-#pragma unroll
-        for (int i = 0; i < H; ++i) {
-            const float send = lower ? a[H + i] : a[i];
-            const float keep = lower ? a[i] : a[H + i];
-            a[i] = keep + rs_dpp<K>(send);
-        }
-        if (N % 2) a[H] = a[2 * H] + rs_dpp<K>(a[2 * H]);
-    }
-}
-
-template <int N, int K>
-__device__ __forceinline__ void rs_ids(int* id, bool* own, bool lower) {
-    constexpr int H = N / 2;
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-        id[i] = lower ? id[i] : id[H + i];
-        own[i] = lower ? own[i] : own[H + i];
-    }
-    if (N % 2) {
-        id[H] = id[2 * H];
-        own[H] = own[2 * H] && lower;
-    }
-}
-
-constexpr int ceil2(int n) { return (n + 1) / 2; }
-
-// Reduces V values over the 64 lanes; afterwards a[0] holds the full sum of
-// value `id` (computed once by rs_layout), written by the lane with own=true.
-template <int V>
-__device__ __forceinline__ void reduce_scatter(float* a, int lane) {
-    constexpr int N1 = V, N2 = ceil2(N1), N3 = ceil2(N2), N4 = ceil2(N3), N5 = ceil2(N4), N6 = ceil2(N5);
-    rs_step<N1, 32>(a, (lane & 32) == 0);
-    rs_step<N2, 16>(a, (lane & 16) == 0);
-    rs_step<N3, 8>(a, (lane & 8) == 0);
-    rs_step<N4, 4>(a, (lane & 4) == 0);
-    rs_step<N5, 2>(a, (lane & 2) == 0);
-    rs_step<N6, 1>(a, (lane & 1) == 0);
-}
-
-template <int V>
-__device__ __forceinline__ void rs_layout(int lane, int* out_id, bool* out_own) {
-    static_assert(V <= 64, "one value per lane after the reduce-scatter");
-    int id[V];
-    bool own[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) { id[i] = i; own[i] = true; }
-    constexpr int N1 = V, N2 = ceil2(N1), N3 = ceil2(N2), N4 = ceil2(N3), N5 = ceil2(N4), N6 = ceil2(N5);
-    rs_ids<N1, 32>(id, own, (lane & 32) == 0);
-    rs_ids<N2, 16>(id, own, (lane & 16) == 0);
-    rs_ids<N3, 8>(id, own, (lane & 8) == 0);
-    rs_ids<N4, 4>(id, own, (lane & 4) == 0);
-    rs_ids<N5, 2>(id, own, (lane & 2) == 0);
-    rs_ids<N6, 1>(id, own, (lane & 1) == 0);
-    *out_id = id[0];
-    *out_own = own[0];
-}
 
 // The walk runs back to front, 16 Gaussians at a time.  List
 // entries and splat records are fetched two batches ahead and the batch's

@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "sort.h"
+#include "wave.h"
 
 namespace xgs {
 
@@ -588,20 +589,26 @@ __global__ void __launch_bounds__(256) vq_rescore_kernel(const float* __restrict
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= N) return;  // uniform per wave
+    // The row's 4 * parts (<= 64) candidates, one per lane; four rounds of a
+    // wavefront minimum in registers (lane swaps and DPP) pick them in order.
     const int nc = 4 * parts;
-    int2 v = lane < nc ? cand[row * nc + lane] : make_int2(0x7FFFFFFF, -1);
+    const int2 v = lane < nc ? cand[row * nc + lane] : make_int2(0x7FFFFFFF, -1);
     int ck = v.x, cc = v.y;
     int pick[4];
+    auto take = [&](int& bk, int& bc, int ok, int oc) {
+        if (cand_before(ok, oc, bk, bc)) { bk = ok; bc = oc; }
+    };
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         int bk = ck, bc = cc;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-            const int ok = __shfl_xor(bk, o, 64), oc = __shfl_xor(bc, o, 64);
-            if (cand_before(ok, oc, bk, bc)) { bk = ok; bc = oc; }
-        }
-        pick[q] = bc;
-        if (cc == bc) cc = -1;  // codewords are distinct across lists
+        take(bk, bc, xlane_partner<32>(bk, lane), xlane_partner<32>(bc, lane));
+        take(bk, bc, xlane_partner<16>(bk, lane), xlane_partner<16>(bc, lane));
+        take(bk, bc, xlane_partner<8>(bk, lane), xlane_partner<8>(bc, lane));
+        take(bk, bc, xlane_partner<4>(bk, lane), xlane_partner<4>(bc, lane));
+        take(bk, bc, xlane_partner<2>(bk, lane), xlane_partner<2>(bc, lane));
+        take(bk, bc, xlane_partner<1>(bk, lane), xlane_partner<1>(bc, lane));
+        pick[q] = __builtin_amdgcn_readfirstlane(bc);
+        if (cc == pick[q]) cc = -1;  // codewords are distinct across lists
     }
     float part[4] = {0.f, 0.f, 0.f, 0.f};
     const float* xr = X + row * D;
@@ -609,6 +616,7 @@ __global__ void __launch_bounds__(256) vq_rescore_kernel(const float* __restrict
 #pragma unroll
     for (int q = 0; q < 4; ++q) er[q] = E + (size_t)(pick[q] >= 0 ? pick[q] : 0) * D;
     if constexpr (V4) {
+#pragma unroll 4
         for (int d4 = lane; d4 < D / 4; d4 += 64) {
             const f32x4_t xv = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t*>(xr) + d4);
 #pragma unroll
@@ -632,9 +640,7 @@ __global__ void __launch_bounds__(256) vq_rescore_kernel(const float* __restrict
         }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) part[q] += __shfl_xor(part[q], o, 64);
+    for (int q = 0; q < 4; ++q) part[q] = wave_sum(part[q]);
     if (lane == 0) {
         float bd = INFINITY;
         int bi = 0x7FFFFFFF;
@@ -647,10 +653,8 @@ __global__ void __launch_bounds__(256) vq_rescore_kernel(const float* __restrict
     if constexpr (CONF) {
         // merge the parts' (m, s): conf = max_k p_k = 1 / sum_k exp(v_k - max v)
         float2 q = lane < parts ? lse[row * parts + lane] : make_float2(-INFINITY, 0.f);
-        float m = q.x;
-        for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-        float sum = q.x > -INFINITY ? q.y * __expf(q.x - m) : 0.f;
-        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        const float m = wave_max(q.x);
+        const float sum = wave_sum(q.x > -INFINITY ? q.y * __expf(q.x - m) : 0.f);
         if (lane == 0) conf[row] = 1.f / sum;
     }
 }
