@@ -762,54 +762,107 @@ __global__ void ema_zero_i32_kernel(int32_t* __restrict__ p) { *p = 0; }
 // issues the loads of 8 rows before adding them in order, so the sum order
 // (and hence the result) does not depend on timing.
 constexpr int EMA_COLS = 4, EMA_ROWS = 8;
+// Rows per piece of the EMA sums: a code with n rows is summed as ceil(n / P)
+// pieces (one workgroup each), so a popular code does not leave one long
+// workgroup behind.
+constexpr int EMA_PIECE = 128;
 
-__global__ void __launch_bounds__(256) ema_accum_kernel(const float* __restrict__ X, int D,
-                                                       const uint32_t* __restrict__ rows,
-                                                       const uint32_t* __restrict__ ranges,
-                                                       float decay, float* __restrict__ N_ema,
-                                                       float* __restrict__ M_ema,
-                                                       float* __restrict__ counts) {
-    __shared__ uint32_t rid[256];
-    const int l = blockIdx.x, t = threadIdx.x;
-    const uint32_t b = ranges[2 * l], e = ranges[2 * l + 1];
+// One workgroup: the pieces of each code (ceil(n_l / P) for its n_l rows) and
+// their exclusive prefix poff[0..K]; each thread takes a contiguous run of
+// codes, so the pieces of a code are consecutive and in row order.
+__global__ void __launch_bounds__(1024) ema_pieces_kernel(const uint32_t* __restrict__ ranges, int K,
+                                                         uint32_t* __restrict__ poff) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (K + 1023) / 1024;
+    const int k0 = min(K, t * per), k1 = min(K, k0 + per);
+    uint32_t c = 0;
+    for (int k = k0; k < k1; ++k) c += (ranges[2 * k + 1] - ranges[2 * k] + EMA_PIECE - 1) / EMA_PIECE;
+    part[t] = c;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t v = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - c;
+    for (int k = k0; k < k1; ++k) {
+        poff[k] = run;
+        run += (ranges[2 * k + 1] - ranges[2 * k] + EMA_PIECE - 1) / EMA_PIECE;
+    }
+    if (t == 1023) poff[K] = part[1023];
+}
+
+// One workgroup per piece: the column sums of its (at most P) rows, added in
+// row order, into partial[piece][:].  The piece's code comes from a binary
+// search of poff.
+__global__ void __launch_bounds__(256) ema_piece_sum_kernel(const float* __restrict__ X, int D,
+                                                           const uint32_t* __restrict__ rows,
+                                                           const uint32_t* __restrict__ ranges,
+                                                           const uint32_t* __restrict__ poff, int K,
+                                                           float* __restrict__ partial) {
+    __shared__ uint32_t rid[EMA_PIECE];
+    const uint32_t pc = blockIdx.x, t = threadIdx.x;
+    if (pc >= poff[K]) return;
+    int lo = 0, hi = K - 1;  // last code with poff <= pc (codes with no pieces share poff)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (poff[mid] <= pc) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t b = ranges[2 * lo] + (pc - poff[lo]) * EMA_PIECE;
+    const uint32_t e = min(b + (uint32_t)EMA_PIECE, ranges[2 * lo + 1]);
+    if (t < e - b) rid[t] = rows[b + t];
+    __syncthreads();
+    const int cnt = (int)(e - b);
+    float* out = partial + (size_t)pc * D;
     for (int d0 = 0; d0 < D; d0 += 256 * EMA_COLS) {
         float acc[EMA_COLS];
 #pragma unroll
         for (int c = 0; c < EMA_COLS; ++c) acc[c] = 0.f;
-        for (uint32_t k0 = b; k0 < e; k0 += 256) {
-            __syncthreads();
-            if (k0 + t < e) rid[t] = rows[k0 + t];
-            __syncthreads();
-            const int cnt = (int)min(256u, e - k0);
-            for (int k = 0; k < cnt; k += EMA_ROWS) {
-                float v[EMA_ROWS][EMA_COLS];
+        for (int k = 0; k < cnt; k += EMA_ROWS) {
+            float v[EMA_ROWS][EMA_COLS];
 #pragma unroll
-                for (int j = 0; j < EMA_ROWS; ++j) {
-                    const bool rok = k + j < cnt;
-                    const size_t base = rok ? (size_t)rid[k + j] * D : 0;
+            for (int j = 0; j < EMA_ROWS; ++j) {
+                const bool rok = k + j < cnt;
+                const size_t base = rok ? (size_t)rid[k + j] * D : 0;
 #pragma unroll
-                    for (int c = 0; c < EMA_COLS; ++c) {
-                        const int d = d0 + t + 256 * c;
-                        v[j][c] = (rok && d < D) ? X[base + d] : 0.f;
-                    }
+                for (int c = 0; c < EMA_COLS; ++c) {
+                    const int d = d0 + t + 256 * c;
+                    v[j][c] = (rok && d < D) ? X[base + d] : 0.f;
                 }
-#pragma unroll
-                for (int j = 0; j < EMA_ROWS; ++j)
-#pragma unroll
-                    for (int c = 0; c < EMA_COLS; ++c) acc[c] += v[j][c];
             }
+#pragma unroll
+            for (int j = 0; j < EMA_ROWS; ++j)
+#pragma unroll
+                for (int c = 0; c < EMA_COLS; ++c) acc[c] += v[j][c];
         }
 #pragma unroll
         for (int c = 0; c < EMA_COLS; ++c) {
             const int d = d0 + t + 256 * c;
-            if (d < D) {
-                float* m = M_ema + (size_t)l * D + d;
-                *m = decay * *m + (1.f - decay) * acc[c];
-            }
+            if (d < D) out[d] = acc[c];
         }
     }
+}
+
+// One workgroup per code: the code's sum is its pieces' sums added in piece
+// order (fixed by the row counts alone, so the result is reproducible), then
+// the EMA step of Eq. (ema_update) on N and M.
+__global__ void __launch_bounds__(256) ema_combine_kernel(const float* __restrict__ partial, int D,
+                                                         const uint32_t* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ poff, float decay,
+                                                         float* __restrict__ N_ema, float* __restrict__ M_ema,
+                                                         float* __restrict__ counts) {
+    const int l = blockIdx.x, t = threadIdx.x;
+    const uint32_t p0 = poff[l], p1 = poff[l + 1];
+    for (int d = t; d < D; d += 256) {
+        float acc = 0.f;
+        for (uint32_t q = p0; q < p1; ++q) acc += partial[(size_t)q * D + d];
+        float* m = M_ema + (size_t)l * D + d;
+        *m = decay * *m + (1.f - decay) * acc;
+    }
     if (t == 0) {
-        const float c = (float)(e - b);
+        const float c = (float)(ranges[2 * l + 1] - ranges[2 * l]);
         N_ema[l] = decay * N_ema[l] + (1.f - decay) * c;
         if (counts) counts[l] = c;
     }
@@ -873,9 +926,13 @@ struct EmaWs {
     int64_t* count;
     float* total;
     int32_t* rank;
+    uint32_t* poff;   // [K + 1] first piece of each code, poff[K] = number of pieces
+    float* partial;   // [max pieces][D] per-piece column sums
 };
 
-static EmaWs carve_ema(void* base, int64_t N, int K, size_t* bytes) {
+inline int64_t ema_max_pieces(int64_t N, int K) { return (N + EMA_PIECE - 1) / EMA_PIECE + (K > 0 ? K : 1); }
+
+static EmaWs carve_ema(void* base, int64_t N, int D, int K, size_t* bytes) {
     Carve c(base);
     EmaWs w;
     const int64_t n1 = N > 0 ? N : 1;
@@ -888,6 +945,8 @@ static EmaWs carve_ema(void* base, int64_t N, int K, size_t* bytes) {
     w.count = c.take<int64_t>(1);
     w.total = c.take<float>(1);
     w.rank = c.take<int32_t>((size_t)(K > 0 ? K : 1));
+    w.poff = c.take<uint32_t>((size_t)(K > 0 ? K + 1 : 2));
+    w.partial = c.take<float>((size_t)ema_max_pieces(N, K) * (size_t)(D > 0 ? D : 1));
     *bytes = c.total();
     return w;
 }
@@ -1043,9 +1102,8 @@ extern "C" xgs_status xgs_vq_assign(const float* X, int64_t N, int32_t D, const 
 }
 
 extern "C" size_t xgs_vq_ema_workspace(int64_t N, int32_t D, int32_t K) {
-    (void)D;
     size_t bytes = 0;
-    carve_ema(nullptr, N < 0 ? 0 : N, K, &bytes);
+    carve_ema(nullptr, N < 0 ? 0 : N, D, K, &bytes);
     return bytes;
 }
 
@@ -1070,7 +1128,7 @@ static xgs_status ema_impl(const char* who, const float* X, const int32_t* idx, 
         return fail(XGS_ERR_INVALID_ARG, w_ + ": dead-code reset needs a reservoir (R >= 1, offset >= 0)");
     if (!aligned(ws, 256)) return fail(XGS_ERR_INVALID_ARG, w_ + ": workspace must be 256-byte aligned");
     size_t need = 0;
-    EmaWs w = carve_ema(ws, N, K, &need);
+    EmaWs w = carve_ema(ws, N, D, K, &need);
     if (!ws || ws_bytes < need) return fail(XGS_ERR_CAPACITY, w_ + ": workspace too small");
     xgs_status s;
     if ((s = fill_u32(w.ranges, 2 * ((int64_t)K + 1), 0u, st))) return s;
@@ -1084,8 +1142,11 @@ static xgs_status ema_impl(const char* who, const float* X, const int32_t* idx, 
     const uint64_t* sk = even ? w.keys : w.keys_alt;
     const uint32_t* sv = even ? w.vals : w.vals_alt;
     if ((s = segment_ranges(sk, w.count, N, 0, w.ranges, st))) return s;
-    hipLaunchKernelGGL(ema_accum_kernel, dim3((unsigned)K), dim3(256), 0, st, X, D, sv, w.ranges, decay, N_ema,
-                       M_ema, counts);
+    hipLaunchKernelGGL(ema_pieces_kernel, dim3(1), dim3(1024), 0, st, w.ranges, K, w.poff);
+    hipLaunchKernelGGL(ema_piece_sum_kernel, dim3((unsigned)ema_max_pieces(N, K)), dim3(256), 0, st, X, D, sv,
+                       w.ranges, w.poff, K, w.partial);
+    hipLaunchKernelGGL(ema_combine_kernel, dim3((unsigned)K), dim3(256), 0, st, w.partial, D, w.ranges, w.poff,
+                       decay, N_ema, M_ema, counts);
     if (dead_on) {
         hipLaunchKernelGGL(ema_dead_rank_kernel, dim3(1), dim3(1024), 0, st, N_ema, K, delta, w.rank, n_dead);
         hipLaunchKernelGGL(ema_dead_reinit_kernel, dim3((unsigned)K), dim3(256), 0, st, w.rank, D, reservoir, R, offset,
