@@ -164,6 +164,28 @@ def test_ema_update_matches_oracle(xgs, mode):
     np.testing.assert_array_equal(np_(Eb), ref)
 
 
+def test_ema_update_skewed_codes_match_oracle(xgs):
+    """One code takes 10,000 rows (79 pieces of 128), one code one row, three
+    codes none, D not a multiple of the column block: the per-piece sums added
+    in piece order against the FP64 oracle."""
+    X, E = vq_case(20_000, 40, 8, 4, seed=5)
+    rng = np.random.default_rng(11)
+    idx = np.where(rng.random(len(X)) < 0.5, 0, rng.integers(1, 5, len(X))).astype(np.int32)
+    idx[idx == 3] = 4
+    idx[17] = 3
+    for mode in (xgs.EMA_PAPER, xgs.EMA_LAPLACE):
+        N0, M0 = oracle.ema_init(E)
+        Nr, Mr, Er, cr, _ = oracle.ema_update(X, idx, N0, M0, 0.9, 1e-5, mode)
+        Ng, Mg, Eg = t(N0.astype(np.float32)), t(M0.astype(np.float32)), t(E)
+        counts = xgs.xgs_vq_ema_update(t(X), t(idx), Ng, Mg, Eg, None, None, 0.9, 1e-5, mode)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(np_(counts), cr)
+        assert cr[0] > 9000 and cr[3] == 1 and cr[5:].sum() == 0
+        assert rel_max(np_(Ng), Nr) < 1e-6
+        assert rel_max(np_(Mg), Mr) < 1e-5
+        assert rel_max(np_(Eg), Er) < 1e-5
+
+
 def test_ema_update_is_bitwise_reproducible(xgs):
     X, E = vq_case(50_000, 64, 128, 16, seed=7)
     idx = t(np.random.default_rng(1).integers(0, 128, len(X)).astype(np.int32))

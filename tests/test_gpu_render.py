@@ -137,6 +137,23 @@ def test_tile_sort_bitexact_large_rects_and_ties(xgs):
     check_sort(xgs, pr, cam, n)
 
 
+def test_tile_sort_above_order_table_limit(xgs):
+    """17,424 tiles (2100 x 2100): above the 16,384 tiles the order kernel
+    sorts, so the table is the identity; keys and ranges stay bit-exact."""
+    rng = np.random.default_rng(4)
+    cam = synth.Camera(width=2100, height=2100, fx=900.0, fy=900.0, cx=1050.0, cy=1050.0)
+    hs, ws, ty, tx = oracle.grid_info(cam)
+    assert tx * ty > 16384
+    n = 6000
+    x0 = rng.integers(0, tx, n); y0 = rng.integers(0, ty, n)
+    x1 = np.minimum(x0 + rng.integers(1, 5, n), tx); y1 = np.minimum(y0 + rng.integers(1, 5, n), ty)
+    rect = np.stack([x0, y0, x1, y1], 1).astype(np.int32)
+    depth = rng.uniform(0.5, 9.0, n)
+    pr = oracle.Projection(None, None, depth, None, None, rect, ((x1 - x0) * (y1 - y0)).astype(np.int64),
+                           np.ones(n, np.int32))
+    check_sort(xgs, pr, cam, n)
+
+
 def test_tile_sort_empty_and_overflow(xgs):
     cam = synth.tiny_camera()
     c = xgs.camera_from(cam)
