@@ -255,7 +255,7 @@ xgs_status xgs_semantic_softmax_bwd(const float* w, const float* dw, int64_t N, 
 /* Decode and masked grid loss (App. D Eq. (loss), App. E F(x) = E^T w(x)):
  * wmap [4+L][Hs][Ws] is xgs_render_fwd's output with the mixture weights as
  * the semantic channels (channels 0..3 are not read); E [L][D] codebook
- * (D % 4 == 0, L D + 65 (L + 17) floats must fit 160 KB of LDS);
+ * (D % 4 == 0, 16-byte aligned);
  * Gstar [D][Hs][Ws] targets; V [Hs][Ws] validity (NULL: all valid).
  *   loss = lambda [ (1/n) sum_valid (1 - cos(G^, G*)) + (1/(n D)) sum_valid |G^ - G*|_1 ],
  *   G^(x) = E^T w(x), cos(a, b) = <a, b> / max(|a| |b|, 1e-8), n = #valid

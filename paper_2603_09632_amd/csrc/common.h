@@ -11,6 +11,8 @@
 
 namespace xgs {
 
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
 // Thresholds of the compositing rule (alpha clamp, skip, stop) and the
 // dilation added to Sigma'.
 constexpr float kAlphaMax = 0.99f;

@@ -53,7 +53,6 @@ __device__ __forceinline__ float sample(const float* __restrict__ Pd, int Wf, co
 }
 
 constexpr int kChanChunk = 8;
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 template <bool VEC>
 __global__ void __launch_bounds__(256) grid_sample_kernel(const float* __restrict__ P, int D, int Hf,

@@ -55,8 +55,6 @@ __device__ __forceinline__ QuadPix quad_pixel(const TileGrid& g) {
     return r;
 }
 
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-
 // 16x16x4 FP32 matrix core op: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; the accumulator holds D[4 (l / 16) + r][l % 16], r = 0..3.
 __device__ __forceinline__ f32x4_t mfma16x16x4(float a, float b, f32x4_t c) {

@@ -5,7 +5,6 @@
 namespace xgs {
 
 constexpr int kRegChunk = 8;
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // Same layout as the grid sample: each thread owns four consecutive grid
 // pixels, looks their labels up once and streams a chunk of channels of

@@ -22,7 +22,6 @@ namespace xgs {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
     uint32_t u = __float_as_uint(f);
