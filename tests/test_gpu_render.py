@@ -137,6 +137,24 @@ def test_tile_sort_bitexact_large_rects_and_ties(xgs):
     check_sort(xgs, pr, cam, n)
 
 
+def test_tile_sort_long_tile_lists(xgs):
+    """Four tiles with 10,000+ instances each (sorted as 4,096-key chunks and
+    merged), many exact depth ties, plus scattered small rectangles."""
+    rng = np.random.default_rng(6)
+    cam = synth.Camera(width=640, height=480, fx=500.0, fy=500.0, cx=320.0, cy=240.0)
+    hs, ws, ty, tx = oracle.grid_info(cam)
+    n = 14_000
+    x0 = rng.integers(0, tx, n); y0 = rng.integers(0, ty, n)
+    x1 = np.minimum(x0 + rng.integers(1, 4, n), tx); y1 = np.minimum(y0 + rng.integers(1, 4, n), ty)
+    big = np.arange(n) < 10_500
+    x0[big], y0[big], x1[big], y1[big] = 3, 2, 5, 4
+    rect = np.stack([x0, y0, x1, y1], 1).astype(np.int32)
+    depth = rng.choice(np.linspace(0.5, 9.0, 300), n)
+    pr = oracle.Projection(None, None, depth, None, None, rect, ((x1 - x0) * (y1 - y0)).astype(np.int64),
+                           np.ones(n, np.int32))
+    check_sort(xgs, pr, cam, n)
+
+
 def test_tile_sort_above_order_table_limit(xgs):
     """17,424 tiles (2100 x 2100): above the 16,384 tiles the order kernel
     sorts, so the table is the identity; keys and ranges stay bit-exact."""
