@@ -22,16 +22,18 @@ namespace xgs {
 // Geometry workspace row per Gaussian (8 floats).
 enum { GW_MX = 0, GW_MY = 1, GW_A = 2, GW_B = 3, GW_C = 4, GW_DEPTH = 5, GW_STRIDE = 8 };
 
-// The walk runs back to front, 16 Gaussians at a time.  List
-// entries and splat records are fetched two batches ahead and the batch's
-// channel rows one batch ahead (vector loads into registers, then LDS), so
-// the per-Gaussian work reads only LDS.  Per Gaussian each pixel recovers
-// T_k, forms w_k = a_k T_k and dL/da_k; the six geometric sums (opacity,
-// conic A B C, mean x y) are reduced over the wavefront at once
-// (reduce-scatter, 6 values) and added atomically.  The channel gradients
-// dL/dc_k = sum_p w_k(p) g(p) of the 16 Gaussians are one 16 x 64 x 48
-// product W^T G on v_mfma_f32_16x16x4_f32: W goes through LDS, G (the wave's
-// upstream gradients in operand layout) is loaded once.
+// The walk runs back to front.  The tile list is read 64 entries at a time
+// (one per lane: list entry and splat record, the next 64 in flight), the
+// splats that can reach alpha >= 1/255 somewhere in the wavefront's quadrant
+// are appended to a ring in LDS (quad_hit; the others are skipped by all 64
+// pixels) and the walk takes the ring 16 at a time, with the channel rows of
+// the next batch in flight.  Per Gaussian each pixel recovers T_k, forms
+// w_k = a_k T_k and dL/da_k; the six geometric sums (opacity, conic A B C,
+// mean x y) are reduced over the wavefront at once (reduce-scatter, 6 values)
+// and added atomically.  The channel gradients dL/dc_k = sum_p w_k(p) g(p) of
+// the batch are one 16 x 64 x 48 product W^T G on v_mfma_f32_16x16x4_f32:
+// W goes through LDS, G (the wave's upstream gradients in operand layout) is
+// loaded once.
 template <int CS, bool GEO, bool EXACT>
 __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
@@ -46,11 +48,11 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
     constexpr int PER = (16 * CHP + 63) / 64;       // channel values per lane per batch
     constexpr int VG = 6;
     __shared__ float wl[64 * 17];
-    __shared__ float4 rec[16][2];
-    __shared__ int gl[16];
+    __shared__ Ring ring;
     __shared__ __align__(16) float chl[16 * CHP];
     const QuadPix P = quad_pixel(g);
     if (P.tile >= g.tiles) return;
+    const QuadRect qr = quad_rect(g, P);
     const int lane = threadIdx.x;
     int my_id = 0;
     bool my_own = false;
@@ -94,57 +96,64 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
     const uint32_t start = uniform(ranges[2 * P.tile]);
     const int top = (int)uniform((uint32_t)jmax);
 
-    // prefetch pipeline (lanes 0..15 own one slot each): entries and records
-    // of batches b+1 (arrived) and b+2 (in flight), channel rows of b+1
-    int g1 = -1, g2 = -1;
-    float4 r10 = make_float4(0.f, 0.f, 0.f, 0.f), r11 = r10, r20 = r10, r21 = r10;
-    float cv[PER];
-    auto fetch = [&](int jb, int& gq, float4& q0, float4& q1) {
-        const int j = jb - 1 - lane;
-        gq = -1;
-        if (lane < 16 && j >= 0) {
-            gq = (int)vals[start + j];
-            q0 = splat[2 * (uint32_t)gq];
-            q1 = splat[2 * (uint32_t)gq + 1];
+    // candidate registers: list entry and splat record of position cpos - 1 - lane
+    int cg = -1;
+    float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
+    auto fetch = [&](int pos) {
+        const int j = pos - 1 - lane;
+        cg = -1;
+        if (j >= 0) {
+            cg = (int)vals[start + (uint32_t)j];
+            c0 = splat[2 * (uint32_t)cg];
+            c1 = splat[2 * (uint32_t)cg + 1];
         }
     };
-    auto fetch_channels = [&](int gq) {
+    int cpos = top, head = 0, tail = 0;
+    // keeps at least two batches in the ring (or everything that is left);
+    // the slots written lie past the two batches being read
+    auto fill = [&]() {
+        while (tail - head < 32 && cpos > 0) {
+            tail = ring_push(ring, tail, cg >= 0 && quad_hit(c0, c1, qr), c0, c1, cg, cpos - 1 - lane);
+            cpos -= 64;
+            fetch(cpos);
+        }
+    };
+    float cv[PER];
+    auto fetch_channels = [&](int base, int n) {
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
             const int e = lane + 64 * t;
             const int k = e / CHP, c = e - k * CHP;
-            const int gk = __shfl(gq, k < 16 ? k : 0, 64);
-            cv[t] = (e < 16 * CHP && gk >= 0 && c < CH && (EXACT || c < 4 + csem))
+            const int gk = (e < 16 * CHP && k < n) ? ring.gid[(base + k) & (kRing - 1)] : -1;
+            cv[t] = (gk >= 0 && c < CH && (EXACT || c < 4 + csem))
                         ? channel_of<CS, EXACT>(colors, splat, features, csem, (uint32_t)gk, c) : 0.f;
         }
     };
-    fetch(top, g1, r10, r11);
-    fetch_channels(g1);
-    fetch(top - 16, g2, r20, r21);
+    fetch(top);
+    fill();
+    __syncthreads();
+    int nb = min(16, tail - head);
+    fetch_channels(head, nb);
     float S = 0.f;
-    for (int jb = top; jb > 0; jb -= 16) {
-        if (lane < 16) {
-            rec[lane][0] = r10;
-            rec[lane][1] = r11;
-            gl[lane] = g1;
-        }
+    while (nb > 0) {
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
             const int e = lane + 64 * t;
             if (e < 16 * CHP) chl[e] = cv[t];
         }
+        fill();
         __syncthreads();
-        g1 = g2; r10 = r20; r11 = r21;
-        fetch_channels(g1);
-        fetch(jb - 32, g2, r20, r21);
+        const int nb2 = min(16, tail - head - nb);
+        fetch_channels(head + nb, nb2);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const int j = jb - 1 - k;
             float w = 0.f;
-            if (j >= 0) {
-                const float4 s0 = rec[k][0];
-                const float4 s1 = rec[k][1];
-                const int gid = gl[k];
+            if (k < nb) {
+                const int at = (head + k) & (kRing - 1);
+                const float4 s0 = ring.rec[at][0];
+                const float4 s1 = ring.rec[at][1];
+                const int gid = ring.gid[at];
+                const int j = ring.pos[at];
                 const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
                 const bool contrib = j < nl && e.alpha >= kAlphaMin;
                 if (__ballot(contrib) != 0ull) {
@@ -212,7 +221,8 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
         // acc[nt][r]: Gaussian slot 4 (lane / 16) + r, channel 16 nt + lane % 16
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int gs = gl[4 * (lane >> 4) + r];
+            const int slot = 4 * (lane >> 4) + r;
+            const int gs = slot < nb ? ring.gid[(head + slot) & (kRing - 1)] : -1;
             if (gs < 0) continue;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
@@ -228,6 +238,8 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
             }
         }
         __syncthreads();
+        head += nb;
+        nb = nb2;
     }
 }
 

@@ -55,6 +55,73 @@ __device__ __forceinline__ QuadPix quad_pixel(const TileGrid& g) {
     return r;
 }
 
+// Pixel-centre rectangle of a wavefront's 8x8 quadrant (clipped to nothing:
+// pixels past the image edge only make the rectangle larger).
+struct QuadRect {
+    float x0, y0, x1, y1;
+};
+
+__device__ __forceinline__ QuadRect quad_rect(const TileGrid& g, const QuadPix& P) {
+    const int lane = threadIdx.x;
+    QuadRect r;
+    r.x0 = P.px - (float)((lane & 7) * g.s);
+    r.y0 = P.py - (float)((lane >> 3) * g.s);
+    r.x1 = r.x0 + (float)(7 * g.s);
+    r.y1 = r.y0 + (float)(7 * g.s);
+    return r;
+}
+
+// Whether a splat can reach alpha >= 1/255 at any pixel centre of the
+// quadrant.  alpha = min(0.99, o exp(-q/2)) >= 1/255 holds exactly where
+// q <= t = 2 ln(255 o); q is convex, so its minimum over the rectangle is 0
+// when the mean lies inside and otherwise lies on an edge, where it is the
+// edge's 1D quadratic at its clamped vertex.  The test errs on the side of
+// keeping: the margin (0.05 + 0.2% of t) is several times the rounding of
+// the per-pixel q (|grad q| <= 2 sqrt(3.4 t) for conics of a Sigma' with the
+// 0.3 dilation, times the ~1e-4 px rounding of dx, dy), so a splat it drops
+// is skipped by every pixel of the quadrant in both passes.
+__device__ __forceinline__ bool quad_hit(const float4 s0, const float4 s1, const QuadRect& r) {
+    const float mx = s0.x, my = s0.y, A = s0.z, B = s0.w, C = s1.x, o = s1.y;
+    const float ex0 = r.x0 - mx, ex1 = r.x1 - mx, ey0 = r.y0 - my, ey1 = r.y1 - my;
+    if (ex0 <= 0.f && ex1 >= 0.f && ey0 <= 0.f && ey1 >= 0.f) return true;
+    const float t = 2.f * __logf(255.f * o);
+    const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
+    auto q = [&](float dx, float dy) { return A * dx * dx + 2.f * B * dx * dy + C * dy * dy; };
+    const float y0 = fminf(fmaxf(-B * ex0 * iC, ey0), ey1);
+    const float y1 = fminf(fmaxf(-B * ex1 * iC, ey0), ey1);
+    const float x0 = fminf(fmaxf(-B * ey0 * iA, ex0), ex1);
+    const float x1 = fminf(fmaxf(-B * ey1 * iA, ex0), ex1);
+    const float best = fminf(fminf(q(ex0, y0), q(ex1, y1)), fminf(q(x0, ey0), q(x1, ey1)));
+    return best <= t * 1.002f + 0.05f;
+}
+
+// Ring of splats that survive the quadrant test, in walk order: the tile
+// list is read 64 candidates at a time (one per lane), the survivors are
+// appended with ballot ranks, and the walk takes them 16 at a time, so each
+// batch of the walk and of its matrix-core channel product holds 16 splats
+// that can touch the wavefront's pixels.
+constexpr int kRing = 128;
+
+struct Ring {
+    float4 rec[kRing][2];
+    int gid[kRing];
+    int pos[kRing];  // list position (offset from the tile's start)
+};
+
+// Appends this lane's candidate when keep is set; returns the new tail.
+__device__ __forceinline__ int ring_push(Ring& q, int tail, bool keep, float4 s0, float4 s1, int gid, int pos) {
+    const uint64_t m = __ballot(keep);
+    if (keep) {
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+        const int at = (tail + below) & (kRing - 1);
+        q.rec[at][0] = s0;
+        q.rec[at][1] = s1;
+        q.gid[at] = gid;
+        q.pos[at] = pos;
+    }
+    return tail + __popcll(m);
+}
+
 // 16x16x4 FP32 matrix core op: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; the accumulator holds D[4 (l / 16) + r][l % 16], r = 0..3.
 __device__ __forceinline__ f32x4_t mfma16x16x4(float a, float b, f32x4_t c) {

@@ -10,17 +10,19 @@ namespace xgs {
 // rows have a compile-time stride and merge into wide scalar loads; otherwise
 // CS only bounds csem and channels >= csem are neither read nor written.
 //
-// A wavefront takes an 8x8 quadrant of a tile and walks the tile list 16 Gaussians at a time.
-// The list entries and splat records of the next batch are fetched by lanes
-// 0..15 with vector loads while the current batch is walked, so the walk
-// reads only LDS (no dependent global load per Gaussian).  For each Gaussian
-// every pixel evaluates alpha and updates T, giving the blend weight
-// w_k(p) = alpha_k T_k (0 for skipped, terminated or absent pairs).  The
-// weights go through LDS (row stride 17: conflict-free both ways) and the
-// channel sums out[p][c] += sum_k w_k(p) chan_k[c] run as a 64 x 16 x 48
-// product on v_mfma_f32_16x16x4_f32, with the channel rows read as vectors
-// (issued before the walk, consumed after it).  The accumulators hold the
-// wave's 64 x (4 + CS) output block until the end.
+// A wavefront takes an 8x8 quadrant of a tile.  It reads the tile list 64
+// entries at a time (one per lane: list entry and splat record), keeps the
+// splats that can reach alpha >= 1/255 somewhere in its quadrant (quad_hit;
+// the others would be skipped by all 64 pixels) and appends them to a ring in
+// LDS; the walk then takes the ring 16 splats at a time.  The next 64 entries
+// are in flight while the ring is walked.  For each splat every pixel
+// evaluates alpha and updates T, giving the blend weight w_k(p) = alpha_k T_k
+// (0 for skipped, terminated or absent pairs).  The weights go through LDS
+// (row stride 17: conflict-free both ways) and the channel sums
+// out[p][c] += sum_k w_k(p) chan_k[c] run as a 64 x 16 x 48 product on
+// v_mfma_f32_16x16x4_f32, with the channel rows read as vectors (issued
+// before the walk, consumed after it).  The accumulators hold the wave's
+// 64 x (4 + CS) output block until the end.
 //
 // The walk is latency-bound (one dependent transmittance chain per pixel), so
 // occupancy pays: at least 3 wavefronts per SIMD (the accumulators stay in
@@ -35,10 +37,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) re
     constexpr int CH = 4 + CS;
     constexpr int NT = (CH + 15) / 16;
     __shared__ float wl[64 * 17];
-    __shared__ float4 rec[16][2];
-    __shared__ int gl[16];
+    __shared__ Ring ring;
     const QuadPix P = quad_pixel(g);
     if (P.tile >= g.tiles) return;
+    const QuadRect qr = quad_rect(g, P);
     const int lane = threadIdx.x;
     f32x4_t acc[4][NT];
 #pragma unroll
@@ -46,37 +48,40 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) re
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     float T = 1.f;
-    uint32_t last = 0;
+    int last = 0;
     bool done = !P.inside;
     const uint32_t start = uniform(ranges[2 * P.tile]);
-    const uint32_t end = uniform(ranges[2 * P.tile + 1]);
-    // prefetch registers (lanes 0..15): entry and record of the next batch
-    int pg = -1;
-    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
-    auto fetch = [&](uint32_t j0) {
-        const uint32_t j = j0 + (uint32_t)lane;
-        pg = -1;
-        if (lane < 16 && j < end) {
-            pg = (int)vals[j];
-            p0 = splat[2 * (uint32_t)pg];
-            p1 = splat[2 * (uint32_t)pg + 1];
+    const int len = (int)(uniform(ranges[2 * P.tile + 1]) - start);
+    // candidate registers: list entry and splat record of position cpos + lane
+    int cg = -1;
+    float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
+    auto fetch = [&](int pos) {
+        cg = -1;
+        if (pos + lane < len) {
+            cg = (int)vals[start + (uint32_t)(pos + lane)];
+            c0 = splat[2 * (uint32_t)cg];
+            c1 = splat[2 * (uint32_t)cg + 1];
         }
     };
-    fetch(start);
-    for (uint32_t j0 = start; j0 < end; j0 += 16) {
+    int cpos = 0, head = 0, tail = 0;
+    fetch(0);
+    for (;;) {
         if (__ballot(!done) == 0ull) break;
-        if (lane < 16) {
-            rec[lane][0] = p0;
-            rec[lane][1] = p1;
-            gl[lane] = pg;
+        // fill the ring to one batch (or the end of the list)
+        while (tail - head < 16 && cpos < len) {
+            tail = ring_push(ring, tail, cg >= 0 && quad_hit(c0, c1, qr), c0, c1, cg, cpos + lane);
+            cpos += 64;
+            fetch(cpos);
         }
+        const int nb = min(16, tail - head);
+        if (nb == 0) break;
         __syncthreads();
-        fetch(j0 + 16);
         // channel rows of this batch in B-operand layout (consumed after the walk)
         float b[4][NT];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            const int gs = gl[4 * kk + (lane >> 4)];
+            const int slot = 4 * kk + (lane >> 4);
+            const int gs = slot < nb ? ring.gid[(head + slot) & (kRing - 1)] : -1;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int c = 16 * nt + (lane & 15);
@@ -86,11 +91,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) re
         }
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const uint32_t j = j0 + k;
             float w = 0.f;
-            if (j < end) {
-                const float4 s0 = rec[k][0];
-                const float4 s1 = rec[k][1];
+            if (k < nb) {
+                const int at = (head + k) & (kRing - 1);
+                const float4 s0 = ring.rec[at][0];
+                const float4 s1 = ring.rec[at][1];
                 const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
                 bool contrib = !done && e.alpha >= kAlphaMin;
                 const float Tn = T * (1.f - e.alpha);
@@ -101,11 +106,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) re
                 if (contrib) {
                     w = e.alpha * T;
                     T = Tn;
-                    last = j - start + 1;
+                    last = ring.pos[at] + 1;
                 }
             }
             wl[lane * 17 + k] = w;
         }
+        head += nb;
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
