@@ -50,6 +50,7 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
     __shared__ float wl[64 * 17];
     __shared__ Ring ring;
     __shared__ __align__(16) float chl[16 * CHP];
+    __shared__ float sdl[GEO ? 64 * 17 : 1];
     const QuadPix P = quad_pixel(g);
     if (P.tile >= g.tiles) return;
     const QuadRect qr = quad_rect(g, P);
@@ -74,19 +75,25 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
             bg[nt][kk] = use ? d_out[c * hw + (size_t)m * g.ws + n] : 0.f;
         }
     }
-    // the pixel's own upstream gradient, for g . c_k
-    float gch[CH];
+    // Upstream gradients as the B operand of S = C G^T (channel 4 kc + lane / 16,
+    // pixel 16 nt + lane % 16): S[k][p] = g(p) . c_k for the batch's 16 splats.
+    constexpr int KC = CHP / 4;
+    float gt[GEO ? KC : 1][4];
+    if constexpr (GEO) {
 #pragma unroll
-    for (int c = 0; c < CH; ++c) gch[c] = 0.f;
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int p = 16 * nt + (lane & 15), c = 4 * kc + (lane >> 4);
+                const int m = qy + (p >> 3), n = qx + (p & 7);
+                const bool use = m < g.hs && n < g.ws && c < CH && (EXACT || c < 4 + csem);
+                gt[kc][nt] = use ? d_out[c * hw + (size_t)m * g.ws + n] : 0.f;
+            }
+    }
     float T = 1.f;
     int nl = 0;
     if (P.inside) {
         const size_t pix = (size_t)P.m * g.ws + P.n;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) gch[c] = GEO ? d_out[c * hw + pix] : 0.f;
-#pragma unroll
-        for (int c = 0; c < CS; ++c)
-            if (EXACT || c < csem) gch[4 + c] = d_out[(4 + c) * hw + pix];
         T = final_T[pix];
         nl = n_last[pix];
     }
@@ -143,8 +150,26 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
         }
         fill();
         __syncthreads();
+        if constexpr (GEO) {
+            // S = C G^T on the matrix cores (A: splat lane % 16, channel 4 kc + lane / 16),
+            // stored as sdl[pixel][splat] for the walk
+            f32x4_t sacc[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) sacc[nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const float a = chl[(lane & 15) * CHP + 4 * kc + (lane >> 4)];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) sacc[nt] = mfma16x16x4(a, gt[kc][nt], sacc[nt]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sdl[(16 * nt + (lane & 15)) * 17 + 4 * (lane >> 4) + r] = sacc[nt][r];
+        }
         const int nb2 = min(16, tail - head - nb);
         fetch_channels(head + nb, nb2);
+        if constexpr (GEO) __syncthreads();
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             float w = 0.f;
@@ -166,16 +191,7 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
                         const float Tk = T * rom;
                         w = e.alpha * Tk;
                         if (GEO) {
-                            const float4* cr = reinterpret_cast<const float4*>(chl + k * CHP);
-                            float sd = 0.f;
-#pragma unroll
-                            for (int c4 = 0; c4 < CHP / 4; ++c4) {
-                                const float4 v = cr[c4];
-                                if (4 * c4 + 0 < CH) sd += gch[4 * c4 + 0] * v.x;
-                                if (4 * c4 + 1 < CH) sd += gch[4 * c4 + 1] * v.y;
-                                if (4 * c4 + 2 < CH) sd += gch[4 * c4 + 2] * v.z;
-                                if (4 * c4 + 3 < CH) sd += gch[4 * c4 + 3] * v.w;
-                            }
+                            const float sd = sdl[lane * 17 + k];
                             const float dalpha = Tk * sd - S * rom;
                             const bool clamped = !(s1.y * e.G < kAlphaMax);
                             const float dq = clamped ? 0.f : dalpha * s1.y * e.G * -0.5f;
