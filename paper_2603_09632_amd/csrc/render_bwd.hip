@@ -57,7 +57,8 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
     const int lane = threadIdx.x;
     int my_id = 0;
     bool my_own = false;
-    if (GEO) rs_layout<VG>(lane, &my_id, &my_own);
+    if (GEO) rs_layout<2 * VG>(lane, &my_id, &my_own);
+    const int my_split = my_id / VG, my_v = my_id - VG * (my_id / VG);  // splat of the pair, sum
     const size_t hw = (size_t)g.hs * g.ws;
     const int fstride = EXACT ? CS : csem;
     const int qx = P.n - (lane & 7), qy = P.m - (lane >> 3);  // quadrant origin
@@ -170,21 +171,27 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
         const int nb2 = min(16, tail - head - nb);
         fetch_channels(head + nb, nb2);
         if constexpr (GEO) __syncthreads();
+        // Splats are taken in pairs: the twelve sums of a pair share one
+        // reduce-scatter and one atomic instruction.
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            float w = 0.f;
-            if (k < nb) {
-                const int at = (head + k) & (kRing - 1);
-                const float4 s0 = ring.rec[at][0];
-                const float4 s1 = ring.rec[at][1];
-                const int gid = ring.gid[at];
-                const int j = ring.pos[at];
-                const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
-                const bool contrib = j < nl && e.alpha >= kAlphaMin;
-                if (__ballot(contrib) != 0ull) {
-                    float a[VG];
+        for (int k2 = 0; k2 < 16; k2 += 2) {
+            float a[2 * VG];
 #pragma unroll
-                    for (int v = 0; v < VG; ++v) a[v] = 0.f;
+            for (int v = 0; v < 2 * VG; ++v) a[v] = 0.f;
+            bool any = false;
+            int gp[2] = {-1, -1};
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int k = k2 + u;
+                float w = 0.f;
+                if (k < nb) {
+                    const int at = (head + k) & (kRing - 1);
+                    const float4 s0 = ring.rec[at][0];
+                    const float4 s1 = ring.rec[at][1];
+                    gp[u] = ring.gid[at];
+                    const int j = ring.pos[at];
+                    const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
+                    const bool contrib = j < nl && e.alpha >= kAlphaMin;
                     if (contrib) {
                         const float om = 1.f - e.alpha;  // >= 0.01
                         const float rom = __builtin_amdgcn_rcpf(om);
@@ -195,34 +202,36 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
                             const float dalpha = Tk * sd - S * rom;
                             const bool clamped = !(s1.y * e.G < kAlphaMax);
                             const float dq = clamped ? 0.f : dalpha * s1.y * e.G * -0.5f;
-                            a[0] = clamped ? 0.f : dalpha * e.G;
-                            a[1] = dq * e.dx * e.dx;
-                            a[2] = 2.f * dq * e.dx * e.dy;
-                            a[3] = dq * e.dy * e.dy;
-                            a[4] = -2.f * dq * (s0.z * e.dx + s0.w * e.dy);
-                            a[5] = -2.f * dq * (s0.w * e.dx + s1.x * e.dy);
+                            a[VG * u + 0] = clamped ? 0.f : dalpha * e.G;
+                            a[VG * u + 1] = dq * e.dx * e.dx;
+                            a[VG * u + 2] = 2.f * dq * e.dx * e.dy;
+                            a[VG * u + 3] = dq * e.dy * e.dy;
+                            a[VG * u + 4] = -2.f * dq * (s0.z * e.dx + s0.w * e.dy);
+                            a[VG * u + 5] = -2.f * dq * (s0.w * e.dx + s1.x * e.dy);
                             S += w * sd;
                         }
                         T = Tk;
-                    }
-                    if (GEO) {
-                        reduce_scatter<VG>(a, lane);
-                        if (my_own) {
-                            float* dst;
-                            switch (my_id) {
-                                case 0: dst = d_opacity + gid; break;
-                                case 1: dst = geo + (size_t)gid * GW_STRIDE + GW_A; break;
-                                case 2: dst = geo + (size_t)gid * GW_STRIDE + GW_B; break;
-                                case 3: dst = geo + (size_t)gid * GW_STRIDE + GW_C; break;
-                                case 4: dst = geo + (size_t)gid * GW_STRIDE + GW_MX; break;
-                                default: dst = geo + (size_t)gid * GW_STRIDE + GW_MY; break;
-                            }
-                            unsafeAtomicAdd(dst, a[0]);
-                        }
+                        any = true;
                     }
                 }
+                wl[lane * 17 + k] = w;
             }
-            wl[lane * 17 + k] = w;
+            if (GEO && k2 < nb && __ballot(any) != 0ull) {
+                reduce_scatter<2 * VG>(a, lane);
+                const int gid = my_split ? gp[1] : gp[0];
+                if (my_own && gid >= 0) {
+                    float* dst;
+                    switch (my_v) {
+                        case 0: dst = d_opacity + gid; break;
+                        case 1: dst = geo + (size_t)gid * GW_STRIDE + GW_A; break;
+                        case 2: dst = geo + (size_t)gid * GW_STRIDE + GW_B; break;
+                        case 3: dst = geo + (size_t)gid * GW_STRIDE + GW_C; break;
+                        case 4: dst = geo + (size_t)gid * GW_STRIDE + GW_MX; break;
+                        default: dst = geo + (size_t)gid * GW_STRIDE + GW_MY; break;
+                    }
+                    unsafeAtomicAdd(dst, a[0]);
+                }
+            }
         }
         __syncthreads();
         f32x4_t acc[NT];

@@ -89,6 +89,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) re
                                 ? channel_of<CS, EXACT>(colors, splat, features, csem, (uint32_t)gs, c) : 0.f;
             }
         }
+        uint32_t nz = 0;  // bit k: this pixel's weight for splat k is nonzero
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             float w = 0.f;
@@ -107,17 +108,21 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) re
                     w = e.alpha * T;
                     T = Tn;
                     last = ring.pos[at] + 1;
+                    nz |= 1u << k;
                 }
             }
             wl[lane * 17 + k] = w;
         }
         head += nb;
         __syncthreads();
+        // a 16-pixel x 4-splat block of weights that is all zero adds nothing
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
+            const uint64_t live = __ballot(((nz >> (4 * kk)) & 0xFu) != 0u);
             const int slot = 4 * kk + (lane >> 4);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
+                if (((live >> (16 * mt)) & 0xFFFFull) == 0ull) continue;
                 const float a = wl[(16 * mt + (lane & 15)) * 17 + slot];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma16x16x4(a, b[kk][nt], acc[mt][nt]);
