@@ -349,6 +349,75 @@ def test_render_bwd_room_300k(xgs, room300k, mode):
     assert all(v <= 1e-3 for v in errs.values()), errs
 
 
+def quadrant_boundary_scene(cam, seed, per_quadrant=4, c_sem=8):
+    """Splats placed so that their alpha = 1/255 contour just reaches one pixel
+    centre of a chosen 8x8 quadrant: the closest centre has q = t (1 - eps),
+    t = 2 ln(255 o), eps in [0.002, 0.01], so that pixel takes the splat while
+    every other pixel of the quadrant may not.  Flat Gaussians turned about the
+    optical axis (identity view) give any 2D covariance A + 0.3 I, independent
+    of where the mean sits; directions, anisotropy and angles are random."""
+    rng = np.random.default_rng(seed)
+    hs, ws, ty, tx = oracle.grid_info(cam)
+    s = cam.stride
+    quads = [(x, y, qx, qy) for y in range(ty) for x in range(tx) for qy in range(2) for qx in range(2)
+             if (y * 16 + qy * 8) < hs and (x * 16 + qx * 8) < ws]
+    means, ls, quats, opac = [], [], [], []
+    for (x, y, qx, qy) in quads:
+        cols = cam.off_x + (x * 16 + qx * 8 + np.arange(8)) * s + 0.5
+        rows = cam.off_y + (y * 16 + qy * 8 + np.arange(8)) * s + 0.5
+        px, py = np.meshgrid(cols, rows)
+        centre = np.array([cols.mean(), rows.mean()])
+        k = 0
+        while k < per_quadrant:
+            a1, a2 = np.exp(rng.uniform(np.log(0.4), np.log(6.0), 2)) * s
+            th = rng.uniform(0.0, np.pi)
+            R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+            A = R @ np.diag([a1 * a1, a2 * a2]) @ R.T
+            conic = np.linalg.inv(A + 0.3 * np.eye(2))
+            o = rng.uniform(0.02, 0.99)
+            target = 2.0 * np.log(255.0 * o) * (1.0 - rng.uniform(0.002, 0.01))
+            phi = rng.uniform(0.0, 2.0 * np.pi)
+            d = np.array([np.cos(phi), np.sin(phi)])
+
+            def qmin(r):
+                dx, dy = px - centre[0] - r * d[0], py - centre[1] - r * d[1]
+                return float((conic[0, 0] * dx * dx + 2 * conic[0, 1] * dx * dy + conic[1, 1] * dy * dy).min())
+
+            lo, hi = 0.0, 400.0 * s
+            if not (qmin(lo) < target < qmin(hi)):
+                continue
+            for _ in range(60):
+                mid = 0.5 * (lo + hi)
+                lo, hi = (mid, hi) if qmin(mid) < target else (lo, mid)
+            u, v = centre + lo * d
+            z = rng.uniform(2.0, 4.0)
+            means.append([(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z])
+            ls.append(np.log([a1 * z / cam.fx, a2 * z / cam.fy, 1e-4 * min(a1, a2) * z / cam.fx]))
+            quats.append([np.cos(th / 2), 0.0, 0.0, np.sin(th / 2)])
+            opac.append(o)
+            k += 1
+    n = len(means)
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    return synth.Scene(f32(means), f32(ls), f32(quats), f32(opac), f32(rng.uniform(0, 1, (n, 3))),
+                       f32(rng.standard_normal((n, c_sem))))
+
+
+@pytest.mark.parametrize("stride,oy,ox", GRID_CASES)
+def test_render_quadrant_culling_boundary(xgs, stride, oy, ox):
+    """Each wavefront drops the splats that cannot reach alpha >= 1/255 at any
+    pixel centre of its 8x8 quadrant.  Splats whose contour only just reaches
+    one centre of a quadrant must still be composited there, in the forward
+    and the backward pass: a wrongly dropped one changes that pixel by about
+    (1/255) T c, far above the 1e-4 bar."""
+    cam = synth.tiny_camera().with_grid(stride, oy, ox)
+    scene = quadrant_boundary_scene(cam, seed=40 + stride)
+    r, ref, amb = staged(xgs, scene, cam)
+    assert check_forward(r, ref, amb, 0.01) < 0.01
+    np.testing.assert_array_equal(np_(r["n_last"])[~amb], ref.n_last[~amb])
+    errs = backward_errors(xgs, r, ref, amb, scene, cam, seed=41)
+    assert all(v <= 1e-3 for v in errs.values()), errs
+
+
 def test_render_bwd_features_only_matches_full(xgs):
     scene, cam = synth.tiny_scene(seed=5), synth.tiny_camera().with_grid(2, 1, 1)
     r = run_render(xgs, scene, cam)
