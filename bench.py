@@ -241,6 +241,10 @@ def main():
                    "instances_last_frame": m_inst},
         "ms": {k: round(v, 4) for k, v in ms.items()},
         "frame_ms_median": round(float(np.median(frame)), 4),
+        "frame_ms_p10": round(float(np.percentile(frame, 10)), 4),
+        "frame_ms_p90": round(float(np.percentile(frame, 90)), 4),
+        # FP32 bytes of X consumed per second by the whole assignment (stage + sweep + rescore)
+        "vq_assign_GBps": round(N * D * 4 / (ms["vq_assign"] * 1e-3) / 1e9, 1),
         "vq_gemm_TFLOPs": round(vq_tflops, 1), "vq_assign_TFLOPs": round(vq_assign_tflops, 1),
         "vq_fp32_plain_ms": round(vq_fp32_ms, 3), "vq_bf16_vs_fp32_same_index": round(vq_same, 6),
         "grid_sample_GBps": round(grid_gbs, 1), "render_fwd_alg_GBps": round(fwd_gbs, 1),
