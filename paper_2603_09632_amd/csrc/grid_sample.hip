@@ -14,20 +14,24 @@ struct Src {
     bool valid;
 };
 
+// I: integer type of the exact source arithmetic.  int32_t when every
+// product below fits (checked by the caller), else int64_t; both give the
+// same integers and hence the same weights.
+template <typename I>
 __device__ __forceinline__ Src source_of(int64_t p, int Ws, int H, int W, int Hf, int Wf, int s,
                                          int oy, int ox, int mode) {
     Src r;
-    const int m = (int)(p / Ws), n = (int)(p - (int64_t)m * Ws);
-    const int64_t u = (int64_t)oy + (int64_t)m * s, v = (int64_t)ox + (int64_t)n * s;
+    const I m = (I)p / (I)Ws, n = (I)p - m * (I)Ws;
+    const I u = (I)oy + m * (I)s, v = (I)ox + n * (I)s;
     r.valid = u < H && v < W;
-    const int64_t by = H > 1 ? H - 1 : 1, bx = W > 1 ? W - 1 : 1;
-    const int64_t ay = u * (Hf - 1), ax = v * (Wf - 1);
-    const int64_t qy = ay / by, ry = ay - qy * by;
-    const int64_t qx = ax / bx, rx = ax - qx * bx;
+    const I by = H > 1 ? H - 1 : 1, bx = W > 1 ? W - 1 : 1;
+    const I ay = u * (I)(Hf - 1), ax = v * (I)(Wf - 1);
+    const I qy = ay / by, ry = ay - qy * by;
+    const I qx = ax / bx, rx = ax - qx * bx;
     if (mode == XGS_GRID_NEAREST) {
         // round half to even of ay/by and ax/bx, exactly
-        int64_t iy = qy + ((2 * ry > by) || (2 * ry == by && (qy & 1)));
-        int64_t ix = qx + ((2 * rx > bx) || (2 * rx == bx && (qx & 1)));
+        I iy = qy + ((2 * ry > by) || (2 * ry == by && (qy & 1)));
+        I ix = qx + ((2 * rx > bx) || (2 * rx == bx && (qx & 1)));
         r.y0 = r.y1 = (int)(iy < Hf - 1 ? iy : Hf - 1);
         r.x0 = r.x1 = (int)(ix < Wf - 1 ? ix : Wf - 1);
         r.wy = r.wx = 0.f;
@@ -52,9 +56,10 @@ __device__ __forceinline__ float sample(const float* __restrict__ Pd, int Wf, co
     return top + s.wy * (bot - top);
 }
 
-constexpr int kChanChunk = 8;
+// channels per thread: the source coordinates of a pixel are computed once per chunk
+constexpr int kChanChunk = 32;
 
-template <bool VEC>
+template <bool VEC, typename I>
 __global__ void __launch_bounds__(256) grid_sample_kernel(const float* __restrict__ P, int D, int Hf,
                                                          int Wf, int H, int W, int s, int oy, int ox,
                                                          int mode, int Hs, int Ws,
@@ -66,20 +71,58 @@ __global__ void __launch_bounds__(256) grid_sample_kernel(const float* __restric
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int64_t p = p0 + k < hw ? p0 + k : hw - 1;
-        src[k] = source_of(p, Ws, H, W, Hf, Wf, s, oy, ox, mode);
+        src[k] = source_of<I>(p, Ws, H, W, Hf, Wf, s, oy, ox, mode);
     }
     const int d0 = blockIdx.y * kChanChunk;
     const int d1 = d0 + kChanChunk < D ? d0 + kChanChunk : D;
     const int64_t plane = (int64_t)Hf * Wf;
-    for (int d = d0; d < d1; ++d) {
-        const float* Pd = P + d * plane;
-        f32x4_t v = {sample(Pd, Wf, src[0]), sample(Pd, Wf, src[1]), sample(Pd, Wf, src[2]),
-                     sample(Pd, Wf, src[3])};
-        float* out = G + (int64_t)d * hw + p0;
-        if (VEC) {
-            __builtin_nontemporal_store(v, reinterpret_cast<f32x4_t*>(out));
-        } else {
-            for (int k = 0; k < 4 && p0 + k < hw; ++k) __builtin_nontemporal_store(v[k], out + k);
+    // Shared sources: the four pixels read the same two source rows and at most
+    // three consecutive source columns, so six loads per channel serve all four
+    // samples (same operands, same arithmetic as sample()).
+    const int xa = src[0].x0;
+    bool shared = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        shared = shared && src[k].valid && src[k].y0 == src[0].y0 && src[k].y1 == src[0].y1 &&
+                 src[k].x0 >= xa && src[k].x1 <= xa + 2;
+    if (shared) {
+        int o0[4], o1[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { o0[k] = src[k].x0 - xa; o1[k] = src[k].x1 - xa; }
+        const int c1 = xa + 1 < Wf ? xa + 1 : Wf - 1, c2 = xa + 2 < Wf ? xa + 2 : Wf - 1;
+        const int ra = src[0].y0 * Wf, rb = src[0].y1 * Wf;
+        auto pick3 = [](float a, float b, float c, int i) { return i == 0 ? a : (i == 1 ? b : c); };
+        for (int d = d0; d < d1; ++d) {
+            const float* Pd = P + d * plane;
+            const float a0 = Pd[ra + xa], a1 = Pd[ra + c1], a2 = Pd[ra + c2];
+            const float b0 = Pd[rb + xa], b1 = Pd[rb + c1], b2 = Pd[rb + c2];
+            f32x4_t v;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float p00 = pick3(a0, a1, a2, o0[k]), p01 = pick3(a0, a1, a2, o1[k]);
+                const float p10 = pick3(b0, b1, b2, o0[k]), p11 = pick3(b0, b1, b2, o1[k]);
+                const float top = p00 + src[k].wx * (p01 - p00);
+                const float bot = p10 + src[k].wx * (p11 - p10);
+                v[k] = top + src[k].wy * (bot - top);
+            }
+            float* out = G + (int64_t)d * hw + p0;
+            if (VEC) {
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4_t*>(out));
+            } else {
+                for (int k = 0; k < 4 && p0 + k < hw; ++k) __builtin_nontemporal_store(v[k], out + k);
+            }
+        }
+    } else {
+        for (int d = d0; d < d1; ++d) {
+            const float* Pd = P + d * plane;
+            f32x4_t v = {sample(Pd, Wf, src[0]), sample(Pd, Wf, src[1]), sample(Pd, Wf, src[2]),
+                         sample(Pd, Wf, src[3])};
+            float* out = G + (int64_t)d * hw + p0;
+            if (VEC) {
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4_t*>(out));
+            } else {
+                for (int k = 0; k < 4 && p0 + k < hw; ++k) __builtin_nontemporal_store(v[k], out + k);
+            }
         }
     }
     if (V && blockIdx.y == 0) {
@@ -112,11 +155,17 @@ extern "C" xgs_status xgs_grid_sample(const float* P, int32_t D, int32_t Hf, int
     const unsigned by = (unsigned)(D > 0 ? (D + kChanChunk - 1) / kChanChunk : 1);
     if (by > 65535) return fail(XGS_ERR_UNSUPPORTED, "xgs_grid_sample: too many channels");
     hipStream_t st = (hipStream_t)stream;
-    if (vec)
-        hipLaunchKernelGGL(grid_sample_kernel<true>, dim3(bx, by), dim3(256), 0, st, P, D, Hf, Wf, H, W,
-                           stride, off_y, off_x, mode, Hs, Ws, G, V);
-    else
-        hipLaunchKernelGGL(grid_sample_kernel<false>, dim3(bx, by), dim3(256), 0, st, P, D, Hf, Wf, H, W,
-                           stride, off_y, off_x, mode, Hs, Ws, G, V);
+    // 32-bit source arithmetic when every intermediate fits: p < hw, u < H + stride,
+    // u (Hf - 1) and v (Wf - 1), and the doubled remainders
+    const int64_t lim = (int64_t(1) << 30);
+    const bool i32 = hw < lim && (int64_t)(H + stride) * Hf < lim && (int64_t)(W + stride) * Wf < lim;
+#define XGS_GS_LAUNCH(V4, I)                                                                         \
+    hipLaunchKernelGGL((grid_sample_kernel<V4, I>), dim3(bx, by), dim3(256), 0, st, P, D, Hf, Wf, H, W, \
+                       stride, off_y, off_x, mode, Hs, Ws, G, V)
+    if (vec && i32) XGS_GS_LAUNCH(true, int32_t);
+    else if (vec) XGS_GS_LAUNCH(true, int64_t);
+    else if (i32) XGS_GS_LAUNCH(false, int32_t);
+    else XGS_GS_LAUNCH(false, int64_t);
+#undef XGS_GS_LAUNCH
     return check_launch("xgs_grid_sample");
 }

@@ -4,12 +4,15 @@
 
 namespace xgs {
 
-constexpr int kRegChunk = 8;
+// channels per thread: the labels of a pixel are looked up once per chunk
+constexpr int kRegChunk = 32;
 
 // Same layout as the grid sample: each thread owns four consecutive grid
 // pixels, looks their labels up once and streams a chunk of channels of
 // Phi[label] out with 16-byte non-temporal stores (Phi stays in cache).
-template <bool VEC>
+// PV: D % 4 == 0 and Phi 16-byte aligned, so four channels of a label row
+// come in one load and are turned into four per-channel output vectors.
+template <bool VEC, bool PV>
 __global__ void __launch_bounds__(256) region_targets_kernel(const int32_t* __restrict__ S, int H, int W,
                                                             const float* __restrict__ Phi, int R, int D, int s,
                                                             int oy, int ox, int Hs, int Ws,
@@ -21,7 +24,8 @@ __global__ void __launch_bounds__(256) region_targets_kernel(const int32_t* __re
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int64_t p = p0 + k < hw ? p0 + k : hw - 1;
-        const int m = (int)(p / Ws), n = (int)(p - (int64_t)m * Ws);
+        // hw < 2^31 (checked by the caller): 32-bit division
+        const int m = (int)p / Ws, n = (int)p - m * Ws;
         const int64_t u = (int64_t)oy + (int64_t)m * s, v = (int64_t)ox + (int64_t)n * s;
         int l = -1;
         if (u < H && v < W) l = S[u * W + v];
@@ -29,15 +33,30 @@ __global__ void __launch_bounds__(256) region_targets_kernel(const int32_t* __re
     }
     const int d0 = blockIdx.y * kRegChunk;
     const int d1 = d0 + kRegChunk < D ? d0 + kRegChunk : D;
-    for (int d = d0; d < d1; ++d) {
-        f32x4_t val;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) val[k] = lab[k] >= 0 ? Phi[(size_t)lab[k] * D + d] : 0.f;
+    auto put = [&](int d, f32x4_t val) {
         float* out = G + (int64_t)d * hw + p0;
         if (VEC) {
             __builtin_nontemporal_store(val, reinterpret_cast<f32x4_t*>(out));
         } else {
             for (int k = 0; k < 4 && p0 + k < hw; ++k) __builtin_nontemporal_store(val[k], out + k);
+        }
+    };
+    if constexpr (PV) {
+        for (int d = d0; d < d1; d += 4) {
+            f32x4_t row[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                row[k] = lab[k] >= 0 ? *reinterpret_cast<const f32x4_t*>(Phi + (size_t)lab[k] * D + d)
+                                     : f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) put(d + j, f32x4_t{row[0][j], row[1][j], row[2][j], row[3][j]});
+        }
+    } else {
+        for (int d = d0; d < d1; ++d) {
+            f32x4_t val;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) val[k] = lab[k] >= 0 ? Phi[(size_t)lab[k] * D + d] : 0.f;
+            put(d, val);
         }
     }
     if (V && blockIdx.y == 0)
@@ -95,13 +114,18 @@ extern "C" xgs_status xgs_region_targets(const int32_t* S, int32_t H, int32_t W,
     const unsigned bx = (unsigned)((hw + 1023) / 1024);
     const unsigned by = (unsigned)(D > 0 ? (D + kRegChunk - 1) / kRegChunk : 1);
     if (by > 65535) return fail(XGS_ERR_UNSUPPORTED, "xgs_region_targets: too many channels");
+    if (hw >= (int64_t(1) << 31) - 4)
+        return fail(XGS_ERR_UNSUPPORTED, "xgs_region_targets: sampled grid above 2^31 pixels");
+    const bool pv = D % 4 == 0 && (R == 0 || aligned(Phi, 16));
     hipStream_t st = (hipStream_t)stream;
-    if (vec)
-        hipLaunchKernelGGL(region_targets_kernel<true>, dim3(bx, by), dim3(256), 0, st, S, H, W, Phi, R, D, stride,
-                           off_y, off_x, Hs, Ws, G, V);
-    else
-        hipLaunchKernelGGL(region_targets_kernel<false>, dim3(bx, by), dim3(256), 0, st, S, H, W, Phi, R, D,
-                           stride, off_y, off_x, Hs, Ws, G, V);
+#define XGS_RT_LAUNCH(V4, P4)                                                                               \
+    hipLaunchKernelGGL((region_targets_kernel<V4, P4>), dim3(bx, by), dim3(256), 0, st, S, H, W, Phi, R, D, stride, \
+                       off_y, off_x, Hs, Ws, G, V)
+    if (vec && pv) XGS_RT_LAUNCH(true, true);
+    else if (vec) XGS_RT_LAUNCH(true, false);
+    else if (pv) XGS_RT_LAUNCH(false, true);
+    else XGS_RT_LAUNCH(false, false);
+#undef XGS_RT_LAUNCH
     return check_launch("xgs_region_targets");
 }
 
