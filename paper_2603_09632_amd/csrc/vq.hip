@@ -658,6 +658,114 @@ __global__ void __launch_bounds__(256) vq_rescore_kernel(const float* __restrict
     }
 }
 
+// Rescore with four rows per wavefront, for up to 16 candidates per row
+// (parts <= 4) and D % 4 == 0: lanes 16 r .. 16 r + 15 hold the candidates of
+// row r, so each of the four selection rounds is one 4-step butterfly within
+// rows of 16 lanes serving all four rows; the 16 FP32 distances (4 rows x 4
+// picks) are summed by one reduce-scatter instead of 16 full wavefront sums.
+// Same candidates, same picks and the same per-lane partial sums as the
+// one-row form; only the order of the final cross-lane additions differs.
+template <bool CONF>
+__global__ void __launch_bounds__(256) vq_rescore4_kernel(const float* __restrict__ X, int64_t N, int D,
+                                                         const float* __restrict__ E,
+                                                         const int2* __restrict__ cand, int parts,
+                                                         int32_t* __restrict__ idx, float* __restrict__ dist,
+                                                         const float2* __restrict__ lse,
+                                                         float* __restrict__ conf) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+    if (row0 >= N) return;  // uniform per wave
+    const int grp = lane >> 4, j = lane & 15;
+    const int64_t myrow = row0 + grp;
+    const int nc = 4 * parts;
+    const int2 v = (j < nc && myrow < N) ? cand[myrow * nc + j] : make_int2(0x7FFFFFFF, -1);
+    int ck = v.x, cc = v.y;
+    int pk[4];
+    auto take = [&](int& bk, int& bc, int ok, int oc) {
+        if (cand_before(ok, oc, bk, bc)) { bk = ok; bc = oc; }
+    };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int bk = ck, bc = cc;
+        take(bk, bc, xlane_partner<8>(bk, lane), xlane_partner<8>(bc, lane));
+        take(bk, bc, xlane_partner<4>(bk, lane), xlane_partner<4>(bc, lane));
+        take(bk, bc, xlane_partner<2>(bk, lane), xlane_partner<2>(bc, lane));
+        take(bk, bc, xlane_partner<1>(bk, lane), xlane_partner<1>(bc, lane));
+        pk[q] = bc;
+        if (cc == bc) cc = -1;  // codewords are distinct across lists
+    }
+    int pick[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pick[r][q] = __builtin_amdgcn_readlane(pk[q], 16 * r);
+    float a[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a[k] = 0.f;
+    const int D4 = D / 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (row0 + r >= N) break;  // uniform
+        const f32x4_t* xr = reinterpret_cast<const f32x4_t*>(X + (row0 + r) * D);
+        const f32x4_t* er[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            er[q] = reinterpret_cast<const f32x4_t*>(E + (size_t)(pick[r][q] >= 0 ? pick[r][q] : 0) * D);
+#pragma unroll 3
+        for (int d4 = lane; d4 < D4; d4 += 64) {
+            const f32x4_t xv = __builtin_nontemporal_load(xr + d4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const f32x4_t ev = er[q][d4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float df = xv[k] - ev[k];
+                    a[4 * r + q] += df * df;
+                }
+            }
+        }
+    }
+    int my_id = 0;
+    bool my_own = false;
+    rs_layout<16>(lane, &my_id, &my_own);
+    reduce_scatter<16>(a, lane);
+    // sum id = 4 r + q now sits in a[0] of its owning lane
+    float sums[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint64_t m = __ballot(my_own && my_id == k);
+        sums[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[0]), (int)__builtin_ctzll(m)));
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (row0 + r >= N) break;
+        float bd = INFINITY;
+        int bi = 0x7FFFFFFF;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (pick[r][q] >= 0 && better(sums[4 * r + q], pick[r][q], bd, bi)) { bd = sums[4 * r + q]; bi = pick[r][q]; }
+        if (lane == r) {
+            idx[row0 + r] = bi;
+            dist[row0 + r] = bd;
+        }
+    }
+    if constexpr (CONF) {
+        // merge the parts' (m, s) of each row within its 16 lanes
+        float2 q = (j < parts && myrow < N) ? lse[myrow * parts + j] : make_float2(-INFINITY, 0.f);
+        float m = q.x;
+        m = fmaxf(m, xlane_dpp<8>(m));
+        m = fmaxf(m, xlane_dpp<4>(m));
+        m = fmaxf(m, xlane_dpp<2>(m));
+        m = fmaxf(m, xlane_dpp<1>(m));
+        float sum = q.x > -INFINITY ? q.y * __expf(q.x - m) : 0.f;
+        sum += xlane_dpp<8>(sum);
+        sum += xlane_dpp<4>(sum);
+        sum += xlane_dpp<2>(sum);
+        sum += xlane_dpp<1>(sum);
+        if (j == 0 && myrow < N) conf[myrow] = 1.f / sum;
+    }
+}
+
 struct VqWs {
     uint16_t* xa;
     uint16_t* ea;
@@ -1032,6 +1140,27 @@ extern "C" xgs_status xgs_vq_candidates(int64_t N, int32_t D, int32_t K, void* w
     return check_launch("xgs_vq_candidates");
 }
 
+// Four rows per wavefront when the rows have at most 16 candidates and the
+// rows are float4-aligned; one row per wavefront otherwise.
+template <bool CONF>
+static void launch_rescore(const float* X, int64_t N, int D, const float* E, int K, const int2* cand, int parts,
+                           int32_t* idx, float* dist, const float2* lse, float* conf, hipStream_t st) {
+    const bool v4 = D % 4 == 0 && aligned(X, 16) && aligned(E, 16);
+    if (v4 && parts <= 4) {
+        const unsigned blocks = (unsigned)((N + 15) / 16);
+        hipLaunchKernelGGL((vq_rescore4_kernel<CONF>), dim3(blocks), dim3(256), 0, st, X, N, D, E, cand, parts, idx,
+                           dist, lse, conf);
+        return;
+    }
+    const unsigned blocks = (unsigned)((N + 3) / 4);
+    if (v4)
+        hipLaunchKernelGGL((vq_rescore_kernel<true, CONF>), dim3(blocks), dim3(256), 0, st, X, N, D, E, K, cand, parts,
+                           idx, dist, lse, conf);
+    else
+        hipLaunchKernelGGL((vq_rescore_kernel<false, CONF>), dim3(blocks), dim3(256), 0, st, X, N, D, E, K, cand,
+                           parts, idx, dist, lse, conf);
+}
+
 extern "C" xgs_status xgs_vq_rescore(const float* X, int64_t N, int32_t D, const float* E, int32_t K,
                                      int32_t* idx, float* dist, void* ws, size_t ws_bytes, xgs_stream_t stream) {
     clear_error();
@@ -1040,14 +1169,7 @@ extern "C" xgs_status xgs_vq_rescore(const float* X, int64_t N, int32_t D, const
     if (xgs_status s = vq_bf16_setup("xgs_vq_rescore", N, D, K, ws, ws_bytes, &plan, &w)) return s;
     if (N == 0) return XGS_OK;
     if (!X || !E || !idx || !dist) return fail(XGS_ERR_INVALID_ARG, "xgs_vq_rescore: null pointer");
-    hipStream_t st = (hipStream_t)stream;
-    const unsigned blocks = (unsigned)((N + 3) / 4);
-    if (D % 4 == 0 && aligned(X, 16) && aligned(E, 16))
-        hipLaunchKernelGGL((vq_rescore_kernel<true, false>), dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand,
-                           plan.parts, idx, dist, nullptr, nullptr);
-    else
-        hipLaunchKernelGGL((vq_rescore_kernel<false, false>), dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand,
-                           plan.parts, idx, dist, nullptr, nullptr);
+    launch_rescore<false>(X, N, D, E, K, w.cand, plan.parts, idx, dist, nullptr, nullptr, (hipStream_t)stream);
     return check_launch("xgs_vq_rescore");
 }
 
@@ -1067,13 +1189,7 @@ extern "C" xgs_status xgs_vq_assign_conf(const float* X, int64_t N, int32_t D, c
     const int64_t gb = ((N + VqCfg::ROWS - 1) / VqCfg::ROWS + 7) / 8 * 8 * plan.parts;
     hipLaunchKernelGGL((vq_gemm_kernel<VqCfg, true>), dim3((unsigned)gb), dim3(VqCfg::THREADS), 0, st, w.xa, N, vq_dp(D) + Q_BK, w.ea, K,
                        plan.parts, plan.tiles_part, plan.seq_bits, w.cand, 1.f / tau, w.lse);
-    const unsigned blocks = (unsigned)((N + 3) / 4);
-    if (D % 4 == 0 && aligned(X, 16) && aligned(E, 16))
-        hipLaunchKernelGGL((vq_rescore_kernel<true, true>), dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand,
-                           plan.parts, idx, dist, w.lse, conf);
-    else
-        hipLaunchKernelGGL((vq_rescore_kernel<false, true>), dim3(blocks), dim3(256), 0, st, X, N, D, E, K, w.cand,
-                           plan.parts, idx, dist, w.lse, conf);
+    launch_rescore<true>(X, N, D, E, K, w.cand, plan.parts, idx, dist, w.lse, conf, st);
     return check_launch("xgs_vq_assign_conf");
 }
 
