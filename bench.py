@@ -198,6 +198,10 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     vq_fp32_ms = e0.elapsed_time(e1)
+    # a seeded row sample of both assignments and the codebook they used, for
+    # the agreement with the FP64 oracle (computed in the CPU-baseline leg)
+    vq_rows = np.sort(np.random.default_rng(33).choice(X.shape[0], 8192, replace=False))
+    vq_sample = (Xh[vq_rows], E.cpu().numpy(), idx.cpu().numpy()[vq_rows], idx32.cpu().numpy()[vq_rows])
     vq_same = float((idx32 == idx).float().mean().item())
 
     ms = {n: float(np.mean(v)) for n, v in per.items()}
@@ -264,6 +268,7 @@ def main():
     # ------------------------------------------------------------ CPU baseline
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, synth)
+        result["vq_index_agreement_fp64"] = vq_agreement(*vq_sample)
     print(json.dumps(result), flush=True)
 
 
@@ -445,6 +450,22 @@ def serving(xgs, synth, dev, n_requests):
             "saturation_frames_per_s": round(sat, 1), "load_points": points,
             "p99_ms_at_80pct": points[-1]["p99_ms"], "peak_hbm_scratch_MB": round(peak, 1),
             "hbm_budget_MB": 4096, "capacity_overflows": overflows, "max_inflight": 8, "hip_graphs": True}
+
+
+def vq_agreement(Xs, Es, idx_bf16, idx_fp32):
+    """Index agreement of the BF16 + rescore and the FP32 plain assignments
+    with the FP64 oracle (brute force) on a seeded row sample; tie-adjusted
+    counts rows whose two best FP64 distances are within 1e-6 relative as
+    agreeing."""
+    import oracle
+
+    ri, d1, d2 = oracle.vq_assign(Xs, Es)
+    tie = (d2 - d1) <= 1e-6 * np.maximum(d1, 1e-30)
+    agree = lambda a: (round(float((a == ri).mean()), 6), round(float(((a == ri) | tie).mean()), 6))
+    b_raw, b_adj = agree(idx_bf16)
+    f_raw, f_adj = agree(idx_fp32)
+    return {"rows": int(len(ri)), "bf16_rescore": b_raw, "bf16_rescore_tie_adjusted": b_adj, "fp32_plain": f_raw,
+            "fp32_plain_tie_adjusted": f_adj}
 
 
 def cpu_baseline(scene, synth):

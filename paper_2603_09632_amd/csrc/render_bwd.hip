@@ -570,12 +570,17 @@ extern "C" xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected
     hipStream_t st = (hipStream_t)stream;
     float* geo = static_cast<float*>(ws);
     xgs_status s;
-    if (g->c_sem > 0 && (s = fill_f32(gr->features, g->n * g->c_sem, 0.f, st))) return s;
+    // the accumulated gradients and the geometry workspace start at zero (one launch)
+    ZeroRanges zr{};
+    if (g->c_sem > 0) { zr.p[zr.k] = reinterpret_cast<uint32_t*>(gr->features); zr.n[zr.k++] = g->n * g->c_sem; }
+    if (geo_on) {
+        zr.p[zr.k] = reinterpret_cast<uint32_t*>(gr->colors); zr.n[zr.k++] = 3 * g->n;
+        zr.p[zr.k] = reinterpret_cast<uint32_t*>(gr->opacity); zr.n[zr.k++] = g->n;
+        zr.p[zr.k] = reinterpret_cast<uint32_t*>(geo); zr.n[zr.k++] = GW_STRIDE * g->n;
+    }
+    if ((s = zero_ranges(zr, st))) return s;
     TileGrid tg = tile_grid(*cam, b->tile_order);
     if (geo_on) {
-        if ((s = fill_f32(gr->colors, 3 * g->n, 0.f, st))) return s;
-        if ((s = fill_f32(gr->opacity, g->n, 0.f, st))) return s;
-        if ((s = fill_f32(geo, GW_STRIDE * g->n, 0.f, st))) return s;
         dispatch_bwd<true>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);
         if ((s = check_launch("xgs_render_bwd pixels"))) return s;
         const CamDevB c = cam_dev_b(*cam);

@@ -38,6 +38,15 @@ xgs_status radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
 xgs_status fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
 xgs_status fill_f32(float* p, int64_t n, float v, hipStream_t stream);
 
+// Zeroes k <= 4 ranges of n[j] 32-bit words at p[j] (any 4-byte alignment) in
+// one launch; ranges with n[j] = 0 are skipped.
+struct ZeroRanges {
+    uint32_t* p[4];
+    int64_t n[4];
+    int k;
+};
+xgs_status zero_ranges(const ZeroRanges& r, hipStream_t stream);
+
 // ranges[2 s] = first, ranges[2 s + 1] = last + 1 position of segment
 // s = keys[i] >> shift among the first *count sorted keys; segments absent
 // from the keys keep whatever the caller filled in.

@@ -20,6 +20,33 @@ xgs_status fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream) {
     return check_launch("fill");
 }
 
+// Zero fill of up to four ranges in one launch (blockIdx.y picks the range):
+// 16-byte stores for the aligned body, 4-byte stores for the ends.
+__global__ void zero_ranges_kernel(ZeroRanges r) {
+    uint32_t* p = r.p[blockIdx.y];
+    const int64_t n = r.n[blockIdx.y];
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t head = (int64_t)(((16 - ((uintptr_t)p & 15)) & 15) / 4);  // words before 16-byte alignment
+    const int64_t h = head < n ? head : n;
+    const int64_t nv = (n - h) / 4;
+    uint4* pv = reinterpret_cast<uint4*>(p + h);
+    for (int64_t i = t0; i < nv; i += stride) pv[i] = make_uint4(0u, 0u, 0u, 0u);
+    const int64_t tail0 = h + 4 * nv;
+    for (int64_t i = t0; i < h + (n - tail0); i += stride) p[i < h ? i : tail0 + (i - h)] = 0u;
+}
+
+xgs_status zero_ranges(const ZeroRanges& r, hipStream_t stream) {
+    int64_t most = 0;
+    for (int j = 0; j < r.k; ++j) most = r.n[j] > most ? r.n[j] : most;
+    if (r.k <= 0 || most <= 0) return XGS_OK;
+    int64_t blocks = (most / 4 + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(zero_ranges_kernel, dim3((unsigned)blocks, (unsigned)r.k), dim3(256), 0, stream, r);
+    return check_launch("zero_ranges");
+}
+
 xgs_status fill_f32(float* p, int64_t n, float v, hipStream_t stream) {
     union { float f; uint32_t u; } c;
     c.f = v;
