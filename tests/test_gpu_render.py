@@ -418,6 +418,28 @@ def test_render_quadrant_culling_boundary(xgs, stride, oy, ox):
     assert all(v <= 1e-3 for v in errs.values()), errs
 
 
+
+@pytest.mark.parametrize("c_sem", [0, 5, 20, 40, 54])
+def test_render_channel_counts(xgs, c_sem):
+    """Channel counts outside the common ones: none (RGB + depth only), counts
+    that run on a wider compiled width with the rest masked (5, 20, 40) and the
+    largest the geometric backward takes (54).  Staged forward and backward
+    against the oracle, and the feature-only backward against the full one."""
+    scene = synth.tiny_scene(seed=11, n=1500, c_sem=c_sem)
+    cam = synth.tiny_camera().with_grid(2, 1, 0) if c_sem % 2 else synth.tiny_camera()
+    r, ref, amb = staged(xgs, scene, cam)
+    assert check_forward(r, ref, amb, 0.01) < 0.01
+    errs = backward_errors(xgs, r, ref, amb, scene, cam, seed=12)
+    assert all(v <= 1e-3 for v in errs.values()), errs
+    if c_sem > 0:
+        hs, ws, _, _ = oracle.grid_info(cam)
+        g = torch.from_numpy(synth.upstream_grad(4 + c_sem, hs, ws, seed=13)).cuda()
+        full = xgs.xgs_render_bwd(r["g"], r["p"], r["b"], r["cam"], g, r["final_T"], r["n_last"])
+        feat = xgs.xgs_render_bwd(r["g"], r["p"], r["b"], r["cam"], g, r["final_T"], r["n_last"],
+                                  flags=xgs.BWD_FEATURES_ONLY)
+        torch.cuda.synchronize()
+        assert rel_l2(np_(feat.features), np_(full.features)) < 1e-6
+
 def test_render_bwd_features_only_matches_full(xgs):
     scene, cam = synth.tiny_scene(seed=5), synth.tiny_camera().with_grid(2, 1, 1)
     r = run_render(xgs, scene, cam)
