@@ -47,7 +47,7 @@ typedef enum {
     XGS_ERR_INVALID_ARG = 1, /* a size, pointer or alignment the call cannot accept */
     XGS_ERR_CAPACITY = 2,    /* a caller-provided buffer or workspace is too small   */
     XGS_ERR_HIP = 3,         /* the HIP runtime reported an error at launch          */
-    XGS_ERR_UNSUPPORTED = 4  /* valid request outside what this build implements     */
+    XGS_ERR_UNSUPPORTED = 4  /* valid request outside what the library implements  */
 } xgs_status;
 
 enum { XGS_TILE = 16 };                     /* tile edge in sampled pixels          */
