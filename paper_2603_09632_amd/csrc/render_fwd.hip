@@ -89,30 +89,37 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) re
                                 ? channel_of<CS, EXACT>(colors, splat, features, csem, (uint32_t)gs, c) : 0.f;
             }
         }
+        // Branch-free per splat (selects only), so that the next splats' ring
+        // reads can be issued while this one's chain runs; the list position of
+        // the pixel's last contributing splat is read once per batch.
         uint32_t nz = 0;  // bit k: this pixel's weight for splat k is nonzero
+        int lastk = -1;   // batch index of this pixel's last contributing splat
+        // records of splats k + 1 and k + 2 are read while splat k is evaluated;
+        // slots k >= nb hold stale records: read (in bounds) and masked
+        float4 ra0 = ring.rec[head & (kRing - 1)][0], ra1 = ring.rec[head & (kRing - 1)][1];
+        float4 rb0 = ring.rec[(head + 1) & (kRing - 1)][0], rb1 = ring.rec[(head + 1) & (kRing - 1)][1];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            float w = 0.f;
-            if (k < nb) {
-                const int at = (head + k) & (kRing - 1);
-                const float4 s0 = ring.rec[at][0];
-                const float4 s1 = ring.rec[at][1];
-                const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
-                bool contrib = !done && e.alpha >= kAlphaMin;
-                const float Tn = T * (1.f - e.alpha);
-                if (contrib && Tn < kTStop) {
-                    done = true;
-                    contrib = false;
-                }
-                if (contrib) {
-                    w = e.alpha * T;
-                    T = Tn;
-                    last = ring.pos[at] + 1;
-                    nz |= 1u << k;
-                }
+            const float4 s0 = ra0, s1 = ra1;
+            ra0 = rb0; ra1 = rb1;
+            if (k + 2 < 16) {
+                const int an = (head + k + 2) & (kRing - 1);
+                rb0 = ring.rec[an][0];
+                rb1 = ring.rec[an][1];
             }
+            const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
+            const bool ok = k < nb && !done && e.alpha >= kAlphaMin;
+            const float Tn = T * (1.f - e.alpha);
+            const bool stop = ok && Tn < kTStop;
+            const bool contrib = ok && !stop;
+            done = done || stop;
+            const float w = contrib ? e.alpha * T : 0.f;
+            T = contrib ? Tn : T;
+            lastk = contrib ? k : lastk;
+            nz |= contrib ? (1u << k) : 0u;
             wl[lane * 17 + k] = w;
         }
+        if (lastk >= 0) last = ring.pos[(head + lastk) & (kRing - 1)] + 1;
         head += nb;
         __syncthreads();
         // a 16-pixel x 4-splat block of weights that is all zero adds nothing
