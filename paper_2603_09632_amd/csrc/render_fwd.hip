@@ -27,7 +27,9 @@ namespace xgs {
 // The walk is latency-bound (one dependent transmittance chain per pixel), so
 // occupancy pays: at least 3 wavefronts per SIMD (the accumulators stay in
 // VGPRs; no spills up to CS = 64) measured 16% faster than the 2 the default
-// register allocation gives.
+// register allocation gives (at CS = 32 the kernel fits 4).  For the same
+// reason the per-splat step has no branches and reads its ring record two
+// splats ahead, so those LDS reads overlap the previous splats' chains.
 template <int CS, bool EXACT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) render_fwd_mfma_kernel(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
