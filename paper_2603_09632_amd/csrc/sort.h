@@ -15,10 +15,11 @@ inline int64_t sort_blocks(int64_t cap) { return (cap + kSortItems - 1) / kSortI
 
 // Exclusive scan of in[0..n) (u32) into out (u64); *total = sum, and when
 // cap >= 0: *count = sum (0 if sum > cap), *status = sum > cap.
-// partials must hold scan_blocks(n) + 1 entries.
+// partials must hold scan_blocks(n) + 1 entries.  zero_p (optional): zero_n
+// u32 words to clear, done by the scan's own launches when possible.
 xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint64_t* partials,
                               int64_t* total, int64_t cap, int64_t* count, int32_t* status,
-                              hipStream_t stream);
+                              uint32_t* zero_p, int64_t zero_n, hipStream_t stream);
 
 // Stable LSD radix sort of the first *count pairs (count <= cap) on key bits
 // [0, key_bits).  Pairs start in (k0, v0); the sorted result is left in

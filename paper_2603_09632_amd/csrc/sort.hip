@@ -70,9 +70,15 @@ __device__ __forceinline__ uint64_t block_incl_scan_256(uint64_t v, uint64_t* sh
     return v + add;
 }
 
+// zero_p (optional): zero_n words cleared by the same grid (a buffer the
+// caller needs cleared before later stages, folded in to save a launch).
 __global__ void __launch_bounds__(256) scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
-                                                         uint64_t* __restrict__ partials) {
+                                                         uint64_t* __restrict__ partials,
+                                                         uint32_t* __restrict__ zero_p, int64_t zero_n) {
     __shared__ uint64_t sh[4];
+    if (zero_p)
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < zero_n; i += (int64_t)gridDim.x * 256)
+            zero_p[i] = 0u;
     int64_t base = (int64_t)blockIdx.x * kScanItems;
     uint64_t s = 0;
 #pragma unroll
@@ -138,12 +144,72 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(const uint32_t* __restr
     }
 }
 
+// Apply without the separate partials pass: block b sums the block totals
+// partials[0..b) itself (nb <= kFusedScanBlocks keeps that cheap), and the
+// last block writes the total, count and status as scan_partials_kernel does.
+constexpr int64_t kFusedScanBlocks = 4096;
+
+__global__ void __launch_bounds__(256) scan_apply_fused_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                              const uint64_t* __restrict__ partials, int64_t nb,
+                                                              uint64_t* __restrict__ out, int64_t* __restrict__ total,
+                                                              int64_t cap, int64_t* __restrict__ count,
+                                                              int32_t* __restrict__ status) {
+    __shared__ uint64_t sh[4];
+    __shared__ uint64_t red[4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint64_t acc = 0;
+    for (int64_t j = t; j < (int64_t)blockIdx.x; j += 256) acc += partials[j];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if (lane == 0) red[w] = acc;
+    __syncthreads();
+    const uint64_t base = (red[0] + red[1]) + (red[2] + red[3]);
+    constexpr int per = kScanItems / 256;  // consecutive items per thread
+    const int64_t first = (int64_t)blockIdx.x * kScanItems + (int64_t)t * per;
+    uint32_t v[per];
+    uint64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < per; ++r) {
+        const int64_t i = first + r;
+        v[r] = i < n ? in[i] : 0u;
+        s += v[r];
+    }
+    const uint64_t incl = block_incl_scan_256(s, sh);
+    uint64_t run = base + incl - s;
+#pragma unroll
+    for (int r = 0; r < per; ++r) {
+        const int64_t i = first + r;
+        if (i < n) out[i] = run;
+        run += v[r];
+    }
+    if (blockIdx.x == nb - 1 && t == 255) {
+        const uint64_t tot = base + incl;  // thread 255's inclusive sum is the block total
+        if (total) *total = (int64_t)tot;
+        if (cap >= 0) {
+            // on overflow nothing is sorted: the lists are empty and status says why
+            *count = (int64_t)(tot > (uint64_t)cap ? 0 : tot);
+            *status = tot > (uint64_t)cap ? 1 : 0;
+        }
+    }
+}
+
 xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint64_t* partials,
                               int64_t* total, int64_t cap, int64_t* count, int32_t* status,
-                              hipStream_t stream) {
+                              uint32_t* zero_p, int64_t zero_n, hipStream_t stream) {
     int64_t nb = scan_blocks(n);
+    if (nb > 0 && nb <= kFusedScanBlocks) {
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, stream, in, n, partials, zero_p,
+                           zero_n);
+        hipLaunchKernelGGL(scan_apply_fused_kernel, dim3((unsigned)nb), dim3(256), 0, stream, in, n, partials, nb,
+                           out, total, cap, count, status);
+        return check_launch("scan");
+    }
+    if (zero_p) {
+        if (xgs_status s = fill_u32(zero_p, zero_n, 0u, stream)) return s;
+    }
     if (nb > 0)
-        hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, stream, in, n, partials);
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, stream, in, n, partials,
+                           (uint32_t*)nullptr, (int64_t)0);
     hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(256), 0, stream, partials, nb, total, cap,
                        count, status);
     if (nb > 0)

@@ -178,10 +178,9 @@ extern "C" xgs_status xgs_tile_sort(const xgs_projected* p, const xgs_camera* ca
     Grid g = grid_of(*cam);
     int64_t tiles = (int64_t)g.tx * g.ty;
     const int64_t cap = b->max_instances;
-    xgs_status s = fill_u32(b->ranges, 2 * tiles, 0u, st);
-    if (s) return s;
-    s = exclusive_scan_u32(p->tiles_touched, n, w.offsets, w.partials, w.total, cap, b->num_instances,
-                           b->status, st);
+    // the scan also clears the per-tile ranges (empty tiles keep (0, 0))
+    xgs_status s = exclusive_scan_u32(p->tiles_touched, n, w.offsets, w.partials, w.total, cap, b->num_instances,
+                                      b->status, b->ranges, 2 * tiles, st);
     if (s) return s;
     int bits = 32 + tile_bits(tiles);
     bool even = radix_passes(bits) % 2 == 0;
