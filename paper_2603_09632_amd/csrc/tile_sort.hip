@@ -7,26 +7,67 @@
 
 namespace xgs {
 
+// A wavefront's 64 consecutive Gaussians own one contiguous run of output
+// positions (the offsets are their exclusive scan), so the wavefront writes
+// that run together: lane l takes positions l, l + 64, ... of the run, finds
+// the owning Gaussian by a 6-step search over the lanes' prefix counts and
+// the tile as the row-major index within its rectangle.  Each store
+// instruction then covers 64 consecutive keys.  Positions at or beyond cap
+// are not written (on overflow the sort sees zero instances anyway).
 __global__ void __launch_bounds__(256) emit_keys_kernel(
     int64_t n, const uint2* __restrict__ tile_rect, const uint32_t* __restrict__ touched,
     const float4* __restrict__ splat, const uint64_t* __restrict__ offsets, int64_t cap, int tiles_x,
     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t cnt = touched[i];
-    if (cnt == 0) return;
-    uint64_t off = offsets[i];
-    if (off + cnt > (uint64_t)cap) return;  // overflow: status already set by the scan
-    uint2 r = tile_rect[i];
-    uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
-    uint32_t dbits = __float_as_uint(splat[2 * i + 1].z);
-    for (uint32_t y = y0; y < y1; ++y)
-        for (uint32_t x = x0; x < x1; ++x) {
-            uint64_t tile = (uint64_t)y * (uint32_t)tiles_x + x;
-            keys[off] = (tile << 32) | dbits;
-            vals[off] = (uint32_t)i;
-            ++off;
+    __shared__ uint32_t s_excl[4][64];
+    __shared__ uint2 s_rect[4][64];
+    __shared__ uint32_t s_dbits[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x) + 64 * w;  // the wave's first Gaussian
+    if (i0 >= n) return;  // uniform per wave
+    const int64_t i = i0 + lane;
+    uint32_t cnt = 0;
+    uint2 r = make_uint2(0u, 0u);
+    uint32_t dbits = 0;
+    if (i < n) {
+        cnt = touched[i];
+        if (cnt > 0) {
+            r = tile_rect[i];
+            dbits = __float_as_uint(splat[2 * i + 1].z);
         }
+    }
+    // inclusive prefix of the counts over the wave
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    const uint32_t total = __shfl(incl, 63, 64);
+    if (total == 0) return;  // uniform
+    s_excl[w][lane] = incl - cnt;
+    s_rect[w][lane] = r;
+    s_dbits[w][lane] = dbits;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint64_t base = offsets[i0];
+    for (uint32_t t = lane; t < total; t += 64) {
+        const uint64_t pos = base + t;
+        if (pos >= (uint64_t)cap) break;  // positions only grow along the loop
+        // owner: the last lane whose exclusive start is <= t (lanes with no
+        // instances share their start with the next lane and are skipped)
+        int lo = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1)
+            if (lo + step < 64 && s_excl[w][lo + step] <= t) lo += step;
+        const uint32_t local = t - s_excl[w][lo];
+        const uint2 rr = s_rect[w][lo];
+        const uint32_t x0 = rr.x & 0xFFFFu, y0 = rr.x >> 16, x1 = rr.y & 0xFFFFu;
+        const uint32_t wd = x1 - x0;
+        const uint32_t y = y0 + local / wd, x = x0 + local - (local / wd) * wd;
+        const uint64_t tile = (uint64_t)y * (uint32_t)tiles_x + x;
+        keys[pos] = (tile << 32) | s_dbits[w][lo];
+        vals[pos] = (uint32_t)(i0 + lo);
+    }
 }
 
 struct SortWs {
