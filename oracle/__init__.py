@@ -35,7 +35,9 @@ T_STOP = 1e-4
 
 def build(force: bool = True) -> str:
     """Compile ``oracle.c`` into ``liboracle.so`` with gcc (IEEE double, no
-    fast-math).  OpenMP parallelises only the row loop of the VQ distances."""
+    fast-math).  OpenMP parallelises the independent loops: grid rows of the
+    compositing walks (the backward adds into the per-Gaussian sums with atomic
+    adds) and rows of X in the VQ distances."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
@@ -54,10 +56,16 @@ def lib():
             build()
         _lib = ctypes.CDLL(_LIB)
         for name in ("orc_project", "orc_composite_fwd", "orc_composite_list", "orc_composite_bwd", "orc_composite_tiles",
-                     "orc_project_bwd", "orc_pose_grad", "orc_vq_assign", "orc_vq_confidence", "orc_grid_info"):
+                     "orc_project_bwd", "orc_pose_grad", "orc_vq_assign", "orc_vq_confidence", "orc_grid_info", "orc_set_threads"):
             getattr(_lib, name).restype = ctypes.c_int
         _lib.orc_bin.restype = ctypes.c_int64
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's parallel loops (n <= 0 leaves the count as it
+    is); returns the count in effect."""
+    return int(lib().orc_set_threads(ctypes.c_int32(n)))
 
 
 def _p(a):

@@ -31,6 +31,7 @@
  *   10..25 world->camera 4x4 row-major.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -315,22 +316,27 @@ int orc_composite_fwd(int64_t n, const double* mean2d, const double* conic, cons
     (void)n;
     cam_t k; read_cam(cam, &k);
     int64_t HW = (int64_t)k.Hs * k.Ws;
-    double* acc = (double*)malloc(sizeof(double) * C);
-    for (int m = 0; m < k.Hs; ++m)
-        for (int nn = 0; nn < k.Ws; ++nn) {
-            int t = (m / ORC_TILE) * k.tx + nn / ORC_TILE;
-            if (tile_mask && !tile_mask[t]) continue;
-            double px = k.ox + (double)nn * k.s + 0.5, py = k.oy + (double)m * k.s + 0.5;
-            uint32_t b = ranges[2 * t], e = ranges[2 * t + 1];
-            double a3[4]; int64_t nl;
-            double T = walk_pixel(px, py, order + b, (int64_t)e - b, mean2d, conic, opac, chan,
-                                  depth, C, acc, &nl, a3);
-            int64_t pix = (int64_t)m * k.Ws + nn;
-            for (int c = 0; c < C; ++c) out[c * HW + pix] = acc[c];
-            final_T[pix] = T; n_last[pix] = nl;
-            if (amb) for (int j = 0; j < 4; ++j) amb[j * HW + pix] = a3[j];
-        }
-    free(acc);
+    /* pixels are independent: rows of the grid may run on several threads */
+#pragma omp parallel
+    {
+        double* acc = (double*)malloc(sizeof(double) * (C > 0 ? C : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int m = 0; m < k.Hs; ++m)
+            for (int nn = 0; nn < k.Ws; ++nn) {
+                int t = (m / ORC_TILE) * k.tx + nn / ORC_TILE;
+                if (tile_mask && !tile_mask[t]) continue;
+                double px = k.ox + (double)nn * k.s + 0.5, py = k.oy + (double)m * k.s + 0.5;
+                uint32_t b = ranges[2 * t], e = ranges[2 * t + 1];
+                double a3[4]; int64_t nl;
+                double T = walk_pixel(px, py, order + b, (int64_t)e - b, mean2d, conic, opac, chan,
+                                      depth, C, acc, &nl, a3);
+                int64_t pix = (int64_t)m * k.Ws + nn;
+                for (int c = 0; c < C; ++c) out[c * HW + pix] = acc[c];
+                final_T[pix] = T; n_last[pix] = nl;
+                if (amb) for (int j = 0; j < 4; ++j) amb[j * HW + pix] = a3[j];
+            }
+        free(acc);
+    }
     return 0;
 }
 
@@ -344,26 +350,30 @@ int orc_composite_tiles(const double* mean2d, const double* conic, const double*
                         const uint32_t* ranges, const double* cam, const int32_t* tiles, int32_t nt,
                         double* out, double* final_T, double* amb) {
     cam_t k; read_cam(cam, &k);
-    double* acc = (double*)malloc(sizeof(double) * C);
-    for (int q = 0; q < nt; ++q) {
-        int t = tiles[q];
-        int ty = t / k.tx, tx = t % k.tx;
-        uint32_t b = ranges[2 * t], e = ranges[2 * t + 1];
-        for (int r = 0; r < ORC_TILE; ++r)
-            for (int c = 0; c < ORC_TILE; ++c) {
-                int m = ty * ORC_TILE + r, nn = tx * ORC_TILE + c;
-                if (m >= k.Hs || nn >= k.Ws) continue;
-                double px = k.ox + (double)nn * k.s + 0.5, py = k.oy + (double)m * k.s + 0.5;
-                double a4[4]; int64_t nl;
-                double T = walk_pixel(px, py, order + b, (int64_t)e - b, mean2d, conic, opac, chan,
-                                      depth, C, acc, &nl, a4);
-                int64_t p = (int64_t)r * ORC_TILE + c;
-                for (int ch = 0; ch < C; ++ch) out[((int64_t)q * C + ch) * 256 + p] = acc[ch];
-                final_T[(int64_t)q * 256 + p] = T;
-                for (int j = 0; j < 4; ++j) amb[((int64_t)q * 4 + j) * 256 + p] = a4[j];
-            }
+#pragma omp parallel
+    {
+        double* acc = (double*)malloc(sizeof(double) * (C > 0 ? C : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int q = 0; q < nt; ++q) {
+            int t = tiles[q];
+            int ty = t / k.tx, tx = t % k.tx;
+            uint32_t b = ranges[2 * t], e = ranges[2 * t + 1];
+            for (int r = 0; r < ORC_TILE; ++r)
+                for (int c = 0; c < ORC_TILE; ++c) {
+                    int m = ty * ORC_TILE + r, nn = tx * ORC_TILE + c;
+                    if (m >= k.Hs || nn >= k.Ws) continue;
+                    double px = k.ox + (double)nn * k.s + 0.5, py = k.oy + (double)m * k.s + 0.5;
+                    double a4[4]; int64_t nl;
+                    double T = walk_pixel(px, py, order + b, (int64_t)e - b, mean2d, conic, opac, chan,
+                                          depth, C, acc, &nl, a4);
+                    int64_t p = (int64_t)r * ORC_TILE + c;
+                    for (int ch = 0; ch < C; ++ch) out[((int64_t)q * C + ch) * 256 + p] = acc[ch];
+                    final_T[(int64_t)q * 256 + p] = T;
+                    for (int j = 0; j < 4; ++j) amb[((int64_t)q * 4 + j) * 256 + p] = a4[j];
+                }
+        }
+        free(acc);
     }
-    free(acc);
     return 0;
 }
 
@@ -415,61 +425,76 @@ int orc_composite_bwd(int64_t n, const double* mean2d, const double* conic, cons
         if (l > cap) cap = l;
     }
     if (cap == 0) return 0;
-    uint32_t* ids = (uint32_t*)malloc(sizeof(uint32_t) * cap);
-    double* al = (double*)malloc(sizeof(double) * cap);
-    double* Ts = (double*)malloc(sizeof(double) * cap);
-    double* Gs = (double*)malloc(sizeof(double) * cap);
-    double* gx = (double*)malloc(sizeof(double) * C);
-    for (int m = 0; m < k.Hs; ++m)
-        for (int nn = 0; nn < k.Ws; ++nn) {
-            int t = (m / ORC_TILE) * k.tx + nn / ORC_TILE;
-            if (tile_mask && !tile_mask[t]) continue;
-            double px = k.ox + (double)nn * k.s + 0.5, py = k.oy + (double)m * k.s + 0.5;
-            int64_t pix = (int64_t)m * k.Ws + nn;
-            for (int c = 0; c < C; ++c) gx[c] = g[c * HW + pix];
-            /* forward walk, recording the blended Gaussians */
-            uint32_t b = ranges[2 * t], e = ranges[2 * t + 1];
-            double T = 1.0; int64_t cnt = 0;
-            for (uint32_t j = b; j < e; ++j) {
-                uint32_t i = order[j];
-                double dx = px - mean2d[2 * i], dy = py - mean2d[2 * i + 1];
-                double q = conic[3 * i] * dx * dx + 2.0 * conic[3 * i + 1] * dx * dy +
-                           conic[3 * i + 2] * dy * dy;
-                double G = exp(-0.5 * q);
-                double oG = opac[i] * G;
-                double alpha = oG < ALPHA_MAX ? oG : ALPHA_MAX;
-                if (alpha < ALPHA_MIN) continue;
-                double Tn = T * (1.0 - alpha);
-                if (Tn < T_STOP) break;
-                ids[cnt] = i; al[cnt] = alpha; Ts[cnt] = T; Gs[cnt] = G; ++cnt;
-                T = Tn;
-            }
-            /* backward over the recorded list */
-            double S = 0.0;
-            for (int64_t r = cnt - 1; r >= 0; --r) {
-                uint32_t i = ids[r];
-                double alpha = al[r], Ti = Ts[r], G = Gs[r];
-                double s = 0.0;
-                for (int c = 0; c < C; ++c) s += gx[c] * chan[(int64_t)i * C + c];
-                double dalpha = Ti * s - S / (1.0 - alpha);
-                S += alpha * Ti * s;
-                double w = alpha * Ti;
-                for (int c = 0; c < C; ++c) d_chan[(int64_t)i * C + c] += w * gx[c];
-                if (opac[i] * G < ALPHA_MAX) {
+    /* pixels are independent; rows of the grid may run on several threads,
+       each accumulating into the per-Gaussian sums with atomic adds */
+#pragma omp parallel
+    {
+        uint32_t* ids = (uint32_t*)malloc(sizeof(uint32_t) * cap);
+        double* al = (double*)malloc(sizeof(double) * cap);
+        double* Ts = (double*)malloc(sizeof(double) * cap);
+        double* Gs = (double*)malloc(sizeof(double) * cap);
+        double* gx = (double*)malloc(sizeof(double) * (C > 0 ? C : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int m = 0; m < k.Hs; ++m)
+            for (int nn = 0; nn < k.Ws; ++nn) {
+                int t = (m / ORC_TILE) * k.tx + nn / ORC_TILE;
+                if (tile_mask && !tile_mask[t]) continue;
+                double px = k.ox + (double)nn * k.s + 0.5, py = k.oy + (double)m * k.s + 0.5;
+                int64_t pix = (int64_t)m * k.Ws + nn;
+                for (int c = 0; c < C; ++c) gx[c] = g[c * HW + pix];
+                /* forward walk, recording the blended Gaussians */
+                uint32_t b = ranges[2 * t], e = ranges[2 * t + 1];
+                double T = 1.0; int64_t cnt = 0;
+                for (uint32_t j = b; j < e; ++j) {
+                    uint32_t i = order[j];
                     double dx = px - mean2d[2 * i], dy = py - mean2d[2 * i + 1];
-                    double A = conic[3 * i], B = conic[3 * i + 1], Cc = conic[3 * i + 2];
-                    d_opac[i] += dalpha * G;
-                    double dq = dalpha * opac[i] * G * (-0.5); /* dL/dq */
-                    d_conic[3 * i] += dq * dx * dx;
-                    d_conic[3 * i + 1] += dq * 2.0 * dx * dy;
-                    d_conic[3 * i + 2] += dq * dy * dy;
-                    /* dq/dmean_x = -2 (A dx + B dy) */
-                    d_mean2d[2 * i] += dq * (-2.0) * (A * dx + B * dy);
-                    d_mean2d[2 * i + 1] += dq * (-2.0) * (B * dx + Cc * dy);
+                    double q = conic[3 * i] * dx * dx + 2.0 * conic[3 * i + 1] * dx * dy +
+                               conic[3 * i + 2] * dy * dy;
+                    double G = exp(-0.5 * q);
+                    double oG = opac[i] * G;
+                    double alpha = oG < ALPHA_MAX ? oG : ALPHA_MAX;
+                    if (alpha < ALPHA_MIN) continue;
+                    double Tn = T * (1.0 - alpha);
+                    if (Tn < T_STOP) break;
+                    ids[cnt] = i; al[cnt] = alpha; Ts[cnt] = T; Gs[cnt] = G; ++cnt;
+                    T = Tn;
+                }
+                /* backward over the recorded list */
+                double S = 0.0;
+                for (int64_t r = cnt - 1; r >= 0; --r) {
+                    uint32_t i = ids[r];
+                    double alpha = al[r], Ti = Ts[r], G = Gs[r];
+                    double s = 0.0;
+                    for (int c = 0; c < C; ++c) s += gx[c] * chan[(int64_t)i * C + c];
+                    double dalpha = Ti * s - S / (1.0 - alpha);
+                    S += alpha * Ti * s;
+                    double w = alpha * Ti;
+                    for (int c = 0; c < C; ++c) {
+#pragma omp atomic
+                        d_chan[(int64_t)i * C + c] += w * gx[c];
+                    }
+                    if (opac[i] * G < ALPHA_MAX) {
+                        double dx = px - mean2d[2 * i], dy = py - mean2d[2 * i + 1];
+                        double A = conic[3 * i], B = conic[3 * i + 1], Cc = conic[3 * i + 2];
+                        double dq = dalpha * opac[i] * G * (-0.5); /* dL/dq */
+#pragma omp atomic
+                        d_opac[i] += dalpha * G;
+#pragma omp atomic
+                        d_conic[3 * i] += dq * dx * dx;
+#pragma omp atomic
+                        d_conic[3 * i + 1] += dq * 2.0 * dx * dy;
+#pragma omp atomic
+                        d_conic[3 * i + 2] += dq * dy * dy;
+                        /* dq/dmean_x = -2 (A dx + B dy) */
+#pragma omp atomic
+                        d_mean2d[2 * i] += dq * (-2.0) * (A * dx + B * dy);
+#pragma omp atomic
+                        d_mean2d[2 * i + 1] += dq * (-2.0) * (B * dx + Cc * dy);
+                    }
                 }
             }
-        }
-    free(ids); free(al); free(Ts); free(Gs); free(gx);
+        free(ids); free(al); free(Ts); free(Gs); free(gx);
+    }
     return 0;
 }
 
@@ -677,4 +702,11 @@ int orc_vq_confidence(int64_t N, int32_t D, const float* X, int32_t K, const flo
         free(dist);
     }
     return 0;
+}
+
+/* Threads used by the parallel loops above (rows of the grid, rows of X);
+   returns the count now in effect. */
+int orc_set_threads(int32_t n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }
