@@ -186,6 +186,44 @@ def test_ema_update_skewed_codes_match_oracle(xgs):
         assert rel_max(np_(Eg), Er) < 1e-5
 
 
+def zipf_codes(n, k, seed):
+    """Code indices with a Zipf(1) popularity over a random permutation of the
+    K codes: the most popular code takes about n / ln(K) rows (dozens of
+    128-row pieces) and a few hundred codes take none."""
+    rng = np.random.default_rng(seed)
+    p = 1.0 / np.arange(1, k + 1)
+    return rng.permutation(k)[rng.choice(k, n, p=p / p.sum())].astype(np.int32)
+
+
+@pytest.mark.parametrize("mode", ["paper", "laplace"])
+def test_ema_update_workload_shape(xgs, mode):
+    """K = 4096 codes of D = 768 (the precision-form codebook) on 65,536 rows:
+    every thread of the per-code kernels handles ceil(K / 1024) = 4 codes, the
+    most popular code is summed from ~60 pieces, and the bf16 shadow and its
+    squared norms are refreshed from the new codebook."""
+    K, D, n = 4096, 768, 65_536
+    X = synth.vq_mixture(n, D, 256, seed=33)
+    E = synth.vq_codebook(K, D, 256, seed=31, centre_seed=30)
+    idx = zipf_codes(n, K, seed=34)
+    m = xgs.EMA_PAPER if mode == "paper" else xgs.EMA_LAPLACE
+    N0, M0 = oracle.ema_init(E)
+    Nr, Mr, Er, cr, _ = oracle.ema_update(X, idx, N0, M0, 0.99, 1e-5, m)
+    assert cr.max() > 50 * 128 and (cr == 0).sum() > 100
+    Ng, Mg, Eg = t(N0.astype(np.float32)), t(M0.astype(np.float32)), t(E)
+    Eb, en = xgs.xgs_vq_prepare(Eg)
+    counts = xgs.xgs_vq_ema_update(t(X), t(idx), Ng, Mg, Eg, Eb, en, 0.99, 1e-5, m)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(np_(counts), cr)
+    assert rel_max(np_(Ng), Nr) < 1e-6
+    assert rel_max(np_(Mg), Mr) < 1e-5
+    assert rel_max(np_(Eg), Er) < 1e-5
+    # shadow and norms of the updated codebook (bf16 rounding of the kernel's E)
+    eb_ref = torch.from_numpy(np_(Eg)).to(torch.bfloat16)
+    np.testing.assert_array_equal(np_(Eb), eb_ref.view(torch.int16).numpy())
+    f = eb_ref.float().numpy().astype(np.float64)
+    assert rel_max(np_(en), (f * f).sum(1)) < 1e-6
+
+
 def test_ema_update_is_bitwise_reproducible(xgs):
     X, E = vq_case(50_000, 64, 128, 16, seed=7)
     idx = t(np.random.default_rng(1).integers(0, 128, len(X)).astype(np.int32))

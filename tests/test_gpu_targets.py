@@ -33,21 +33,24 @@ def test_region_targets_bitexact(xgs, H, W, R, D, s, oy, ox):
     np.testing.assert_array_equal(np_(G), Gr.astype(np.float32))
 
 
-def test_occluder_mask_matches_the_rule_on_the_kernels_projection(xgs):
-    """Staged: the rule applied in binary32 to the GPU's own projection (the
-    decision is an integer function of those values)."""
+def test_occluder_mask_matches_the_rule_on_the_oracles_projection(xgs):
+    """Staged: both sides apply the rule in binary32 to the oracle's projection
+    rounded to binary32 (the decision is an integer function of those
+    values), against a depth map made from the oracle's render pushed back by
+    15% on a band."""
+    from gpu_util import splat_from_oracle
     scene = synth.room_scene(300_000, seed=2, c_sem=1)
     cam = synth.room_camera(640, 480, 525.0, synth.room_trajectory(100, seed=10)[20])
-    r = run_render(xgs, scene, cam)
-    out = np_(r["out"])
-    # the estimated depth map: the rendered depth pushed back by 15% on a band
-    dm = out[3].copy()
-    dm[100:200] *= 1.15
-    prune, count = xgs.xgs_occluder_mask(r["p"], scene.n, t(dm), 0.1)
+    pr = oracle.project(scene, cam)
+    p, sp = splat_from_oracle(xgs, pr, scene.opacity, scene.n)
+    tiles = np.zeros(oracle.grid_info(cam)[2] * oracle.grid_info(cam)[3], np.uint8)
+    tiles[::3] = 1
+    dm = oracle.render(scene, cam, tiles).out[3].astype(np.float32)
+    dm[100:200] *= np.float32(1.15)
+    prune, count = xgs.xgs_occluder_mask(p, scene.n, t(dm), 0.1)
     torch.cuda.synchronize()
-    sp = np_(r["p"].splat).reshape(-1, 8)
-    vis = np_(r["p"].radius) > 0
-    ref = oracle.occluder_mask(sp[:, 0:2], sp[:, 6], vis, dm.astype(np.float32), np.float32(0.1))
+    vis = pr.visible == 1
+    ref = oracle.occluder_mask(sp[:, 0:2], sp[:, 6], vis, dm, np.float32(0.1))
     got = np_(prune)
     np.testing.assert_array_equal(got, ref)
     assert int(np_(count)[0]) == int(ref.sum()) and ref.sum() > 0

@@ -41,9 +41,10 @@ def posed_camera(cam):
     return replace(cam, viewmat=oracle.se3_exp(np.r_[0.05, -0.03, 0.1, 0.04, -0.06, 0.02]).astype(np.float32))
 
 
-def test_pose_gradient_staged_on_the_oracle_adjoint(xgs):
-    """The GPU backward and pose reduction run on the oracle's upstream
-    gradient; the pose gradient matches the oracle's within 1e-3."""
+def test_pose_gradient_tiny_end_to_end(xgs):
+    """Tiny scene at a posed camera: the GPU's own projection, binning,
+    backward and pose reduction under a seeded upstream gradient; the pose
+    gradient matches the oracle's within 1e-3 of its largest component."""
     scene = synth.tiny_scene(seed=3)
     cam = posed_camera(synth.tiny_camera())
     hs, ws, _, _ = oracle.grid_info(cam)
@@ -77,21 +78,22 @@ def test_pose_gradient_room_300k(xgs):
 
 
 def test_tracking_step_against_a_perturbed_target(xgs):
-    """Target = the GPU render at a pose moved by a small twist; the tracking
-    step at the original pose: its loss equals the oracle's tracking loss of
-    the same maps, and the pose gradient points downhill (a small step along
-    -grad lowers the loss)."""
+    """Target = the oracle's render at a pose moved by a small twist; the
+    tracking step at the original pose: its loss equals the oracle's tracking
+    loss of the oracle's render at that pose (relative 1e-4), and the pose
+    gradient points downhill (a small step along -grad lowers the loss)."""
     scene = synth.tiny_scene(seed=5)
     cam = posed_camera(synth.tiny_camera())
     xi = np.r_[0.01, 0.0, -0.01, 0.0, 0.01, 0.0]
     cam_t = replace(cam, viewmat=(oracle.se3_exp(xi) @ cam.viewmat).astype(np.float32))
-    tgt = run_render(xgs, scene, cam_t)
-    img, dep = tgt["out"][:3].contiguous(), tgt["out"][3].contiguous()
+    tgt = oracle.render(scene, cam_t).out
+    img_np, dep_np = tgt[:3].astype(np.float32), tgt[3].astype(np.float32)
+    img, dep = t(img_np), t(dep_np)
     r = run_render(xgs, scene, cam)
     loss, d_pose, out = xgs.tracking_step(r["g"], r["p"], r["b"], r["cam"], img, dep, 0.5)
     torch.cuda.synchronize()
-    ref, _ = oracle.track_loss(np_(out), np_(img), np_(dep), 0.5)
-    assert abs(float(np_(loss)[0]) - ref) <= 1e-5 * ref
+    ref, _ = oracle.track_loss(oracle.render(scene, cam).out, img_np, dep_np, 0.5)
+    assert abs(float(np_(loss)[0]) - ref) <= 1e-4 * ref
     d = np_(d_pose).astype(np.float64)
     step = -1e-3 * d / np.linalg.norm(d)
     cam_s = replace(cam, viewmat=(oracle.se3_exp(step) @ cam.viewmat).astype(np.float32))

@@ -139,6 +139,26 @@ def test_ema_constant_input_closed_form(orc):
         np.testing.assert_allclose(E[K - 1], lam ** t * E0[K - 1] / (lam ** t + eps), rtol=1e-12)
 
 
+def test_ema_hand_computed_two_codes(orc):
+    """K = 2, D = 2, three rows, decay 0.5, eps 0.1, worked by hand from
+    Eq. (ema_update): c = (2, 1), s = ((8, 2), (0, 4)), N = (1.5, 1.0),
+    M = ((4.5, 1), (0, 3)).  PAPER: E = M / (N + eps).  LAPLACE: n = 2.5,
+    Ntilde = (N + eps) / (n + 2 eps) n = (1.6, 1.1) * 2.5 / 2.7."""
+    E0 = np.array([[1.0, 0.0], [0.0, 2.0]])
+    X = np.array([[3.0, 1.0], [5.0, 1.0], [0.0, 4.0]])
+    idx = np.array([0, 0, 1])
+    N, M = orc.ema_init(E0)
+    Np, Mp, Ep, cnt, sums = orc.ema_update(X, idx, N, M, 0.5, 0.1, orc.PAPER)
+    np.testing.assert_array_equal(cnt, [2.0, 1.0])
+    np.testing.assert_array_equal(sums, [[8.0, 2.0], [0.0, 4.0]])
+    np.testing.assert_array_equal(Np, [1.5, 1.0])
+    np.testing.assert_array_equal(Mp, [[4.5, 1.0], [0.0, 3.0]])
+    np.testing.assert_allclose(Ep, [[2.8125, 0.625], [0.0, 3.0 / 1.1]], rtol=1e-15)
+    _, _, El, _, _ = orc.ema_update(X, idx, N, M, 0.5, 0.1, orc.LAPLACE)
+    # E_0 = (4.5, 1) * 2.7 / (1.6 * 2.5) = (3.0375, 0.675); E_1 = (0, 3) * 2.7 / (1.1 * 2.5)
+    np.testing.assert_allclose(El, [[3.0375, 0.675], [0.0, 8.1 / 2.75]], rtol=1e-15)
+
+
 def test_ema_conservation_and_laplace_mass(orc):
     X = synth.vq_mixture(2000, 16, 8, seed=4)
     E0 = synth.vq_codebook(32, 16, 8, seed=5, centre_seed=4)
@@ -147,10 +167,13 @@ def test_ema_conservation_and_laplace_mass(orc):
     N1, M1, E1, cnt, sums = orc.ema_update(X, idx, N, M, 0.99, 1e-5, orc.LAPLACE)
     assert cnt.sum() == len(X)
     np.testing.assert_allclose(sums.sum(0), X.astype(np.float64).sum(0), rtol=1e-12, atol=1e-12)
-    tot = N1.sum()
-    nt = (N1 + 1e-5) / (tot + 32 * 1e-5) * tot
-    assert nt.sum() == pytest.approx(tot, rel=1e-14)
-    np.testing.assert_allclose(E1 * nt[:, None], M1, rtol=1e-12)
+    # Laplace smoothing redistributes the counts without changing their total:
+    # the per-code divisors M_l / E_l sum to sum_l N_l, and each divisor is
+    # N_l shifted towards the mean by eps
+    div = (M1 / E1)[:, 0]
+    np.testing.assert_allclose(M1 / E1, np.repeat(div[:, None], 16, 1), rtol=1e-12)
+    assert div.sum() == pytest.approx(N1.sum(), rel=1e-13)
+    assert np.all(np.sign(div - N1) == np.sign(N1.mean() - N1))
     # with no samples the EMA only decays
     N2, M2, _, _, _ = orc.ema_update(X[:0], idx[:0], N, M, 0.99, 1e-5, orc.LAPLACE)
     np.testing.assert_allclose(N2, 0.99 * N)
