@@ -178,6 +178,22 @@ size_t xgs_tile_sort_workspace(int64_t n, int64_t max_instances, int32_t num_til
 xgs_status xgs_tile_sort(const xgs_projected* p, const xgs_camera* cam, int64_t n, void* ws,
                          size_t ws_bytes, xgs_binning* b, xgs_stream_t stream);
 
+/* Allocation-free tile sort, for callers that cannot allocate device memory
+ * or pass a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * xgs_tile_sort, without ws: the sort runs in a scratch array of
+ * xgs_tile_sort_noalloc_max_bytes() bytes (64 MiB: n = 2M Gaussians with
+ * max_instances = 4M fit) that the library holds on each GPU it runs on until
+ * the process ends.  A call whose xgs_tile_sort_workspace(n, max_instances,
+ * tiles) exceeds that size returns XGS_ERR_CAPACITY before any launch.  The
+ * entry point calls no hipMalloc, hipFree or allocating library routine.
+ * All calls on one GPU share its scratch (later calls overwrite it): calls
+ * that overlap on one GPU (different streams or threads without ordering)
+ * race and must not be issued. */
+size_t xgs_tile_sort_noalloc_max_bytes(void);
+xgs_status xgs_tile_sort_noalloc(const xgs_projected* p, const xgs_camera* cam, int64_t n, xgs_binning* b,
+                                 xgs_stream_t stream);
+
 /* -------------------------------------------------- a3: render forward
  * Front-to-back alpha blending, Eq. (rendering): for every grid pixel walk its
  * tile's list, alpha = min(0.99, o exp(-q/2)); skip alpha < 1/255; stop

@@ -32,7 +32,8 @@ BWD_ALL, BWD_FEATURES_ONLY = 0, 1
 
 __all__ = [
     "XgsError", "Gaussians", "Projected", "Binning", "camera", "camera_from", "grid_dims",
-    "xgs_project", "xgs_project_posed", "alloc_binning", "xgs_tile_sort", "xgs_render_fwd", "xgs_render_bwd",
+    "xgs_project", "xgs_project_posed", "alloc_binning", "xgs_tile_sort", "xgs_tile_sort_noalloc", "xgs_render_fwd",
+    "xgs_render_bwd",
     "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_stage", "xgs_vq_candidates", "xgs_vq_rescore",
     "vq_assign_workspace", "xgs_vq_ema_update", "xgs_semantic_softmax", "xgs_semantic_softmax_bwd",
     "xgs_semantic_loss", "semantic_step", "xgs_pose_grad", "xgs_tracking_loss", "tracking_step", "xgs_region_targets",
@@ -198,6 +199,15 @@ def xgs_tile_sort(p: Projected, cam, n: int, b: Binning, stream=None) -> Binning
     ps, bs = p.struct(), b.struct()
     check(lib.xgs_tile_sort(ctypes.byref(ps), ctypes.byref(c), int(n), _ptr(b.workspace), b.workspace.numel(),
                             ctypes.byref(bs), _stream(stream)), "xgs_tile_sort")
+    return b
+
+
+def xgs_tile_sort_noalloc(p: Projected, cam, n: int, b: Binning, stream=None) -> Binning:
+    """xgs_tile_sort in the library's own scratch (b.workspace is not used)."""
+    c = camera_from(cam)
+    ps, bs = p.struct(), b.struct()
+    check(lib.xgs_tile_sort_noalloc(ctypes.byref(ps), ctypes.byref(c), int(n), ctypes.byref(bs), _stream(stream)),
+          "xgs_tile_sort_noalloc")
     return b
 
 

@@ -56,6 +56,8 @@ SIGNATURES = {
     "xgs_tile_sort_workspace": (c_size_t, [c_int64, c_int64, c_int32]),
     "xgs_tile_sort": (c_int32, [P(XgsProjected), P(XgsCamera), c_int64, c_void_p, c_size_t,
                                 P(XgsBinning), c_void_p]),
+    "xgs_tile_sort_noalloc_max_bytes": (c_size_t, []),
+    "xgs_tile_sort_noalloc": (c_int32, [P(XgsProjected), P(XgsCamera), c_int64, P(XgsBinning), c_void_p]),
     "xgs_render_fwd": (c_int32, [P(XgsGaussians), P(XgsProjected), P(XgsBinning), P(XgsCamera),
                                  c_void_p, c_void_p, c_void_p, c_void_p]),
     "xgs_render_bwd_workspace": (c_size_t, [c_int64]),

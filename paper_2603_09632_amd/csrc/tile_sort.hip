@@ -3,9 +3,21 @@
 // positive IEEE binary32 values order like their bit patterns.  Keys are
 // emitted in Gaussian order and sorted with a stable LSD radix sort, so equal
 // keys keep ascending Gaussian index.
+#include <mutex>
+
 #include "sort.h"
 
 namespace xgs {
+
+// Scratch of the allocation-free entry point: the library's own workspace
+// for the sort, one copy per GPU (each device that runs the entry point holds
+// it until the process ends).  In host code the name is a host-side stand-in:
+// its device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kSortScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kSortScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+static void* g_scratch_ptr[kMaxScratchDevices];
+static std::mutex g_scratch_mu;
 
 // A wavefront's 64 consecutive Gaussians own one contiguous run of output
 // positions (the offsets are their exclusive scan), so the wavefront writes
@@ -245,4 +257,45 @@ extern "C" xgs_status xgs_tile_sort(const xgs_projected* p, const xgs_camera* ca
                                tiles, b->tile_order);
     }
     return check_launch("xgs_tile_sort order");
+}
+
+extern "C" size_t xgs_tile_sort_noalloc_max_bytes(void) { return kSortScratchBytes; }
+
+extern "C" xgs_status xgs_tile_sort_noalloc(const xgs_projected* p, const xgs_camera* cam, int64_t n,
+                                            xgs_binning* b, xgs_stream_t stream) {
+    clear_error();
+    if (!p || !cam || !b) return fail(XGS_ERR_INVALID_ARG, "xgs_tile_sort_noalloc: null argument");
+    if (xgs_status s = validate_camera(cam)) return s;
+    if (n < 0 || b->max_instances < 0)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_tile_sort_noalloc: negative size");
+    const Grid g = grid_of(*cam);
+    const size_t need = xgs_tile_sort_workspace(n, b->max_instances, g.tx * g.ty);
+    if (need > kSortScratchBytes)
+        return fail(XGS_ERR_CAPACITY, "xgs_tile_sort_noalloc: n = " + std::to_string(n) + " and max_instances = " +
+                                          std::to_string(b->max_instances) + " need " + std::to_string(need) +
+                                          " bytes of scratch, above the fixed " + std::to_string(kSortScratchBytes) +
+                                          " (use xgs_tile_sort with a workspace)");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(XGS_ERR_HIP, std::string("xgs_tile_sort_noalloc: hipGetDevice: ") +
+                                                      hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(XGS_ERR_UNSUPPORTED, "xgs_tile_sort_noalloc: device index above 63");
+    void* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            // with the device current: each GPU holds its own copy of the array
+            e = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+            if (e != hipSuccess) {
+                g_scratch_ptr[dev] = nullptr;
+                return fail(XGS_ERR_HIP, std::string("xgs_tile_sort_noalloc: hipGetSymbolAddress: ") +
+                                             hipGetErrorString(e));
+            }
+        }
+        ws = g_scratch_ptr[dev];
+    }
+    // every kernel of the sort writes the scratch words it later reads, so
+    // nothing has to be cleared between calls
+    return xgs_tile_sort(p, cam, n, ws, kSortScratchBytes, b, stream);
 }
