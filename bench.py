@@ -31,6 +31,9 @@ METRIC = "fwd+bwd ms/frame at 1M Gaussians 1200x680 32-ch"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
+# FP32 lane operations per second with packed FP32 off (the build disables it):
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz; an FMA counts as one operation
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(msg):
@@ -217,22 +220,17 @@ def main():
     vq_assign_tflops = vq_flop / (ms["vq_assign"] * 1e-3) / 1e12
     grid_bytes = 512 * 480 * 640 * 4 + 480 * 640 + 512 * 30 * 40 * 4
     grid_gbs = grid_bytes / (ms["grid_sample"] * 1e-3) / 1e9
-    # compositing forward: per instance val + splat + rgb + features; per pixel outputs
-    fwd_bytes = m_inst * (4 + 32 + 12 + 4 * scene.c_sem) + hs * ws * 4 * (C + 2)
-    fwd_gbs = fwd_bytes / (ms["render_fwd"] * 1e-3) / 1e9
-    timed = {"render_bwd": ms["render_bwd"], "vq_gemm": ms["vq_gemm"], "render_fwd": ms["render_fwd"]}
-    dominant = max(timed, key=timed.get)
-    if dominant == "vq_gemm":
-        roof = {"kernel": "vq_gemm_kernel", "bound": "mfma", "achieved": round(vq_tflops, 2),
-                "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(vq_tflops / BF16_PEAK_TFLOPS, 4),
-                "traffic": traffic_for("vq_gemm_kernel", ["vq.hip"], vq_flop),
-                "algorithmic": f"2*N*K*D = {vq_flop:.3e} flop per launch (N=816000, K=4096, D=768)"}
-    else:
-        bwd_bytes = fwd_bytes + g.n * 4 * (3 + 3 + 4 + 1 + 3 + scene.c_sem) * 2
-        a = bwd_bytes / (ms[dominant] * 1e-3) / 1e9
-        roof = {"kernel": dominant, "bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None,
-                "algorithmic": f"{bwd_bytes:.3e} bytes per launch"}
+    comp = compositing_work(xgs, g, p, b, cams[args.warmup + args.steps - 1], out, fT, nl, scene.c_sem, m_inst,
+                            ms["render_fwd"], ms["render_bwd"])
+    roofs = [
+        {"kernel": "vq_gemm_kernel", "bound": "mfma", "achieved": round(vq_tflops, 2), "peak": BF16_PEAK_TFLOPS,
+         "unit": "TFLOP/s", "frac": round(vq_tflops / BF16_PEAK_TFLOPS, 4),
+         "traffic": traffic_for("vq_gemm_kernel", ["vq.hip"], vq_flop),
+         "algorithmic": f"2*N*K*D = {vq_flop:.3e} flop per launch (N=816000, K=4096, D=768)", "ms": ms["vq_gemm"]},
+        comp.pop("roofline_fwd"), comp.pop("roofline_bwd"),
+    ]
+    roof = dict(max(roofs, key=lambda r: r["ms"]))
+    roof.pop("ms")
 
     result = {
         "metric": METRIC, "value": round(value, 4), "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
@@ -251,11 +249,14 @@ def main():
         "vq_assign_GBps": round(N * D * 4 / (ms["vq_assign"] * 1e-3) / 1e9, 1),
         "vq_gemm_TFLOPs": round(vq_tflops, 1), "vq_assign_TFLOPs": round(vq_assign_tflops, 1),
         "vq_fp32_plain_ms": round(vq_fp32_ms, 3), "vq_bf16_vs_fp32_same_index": round(vq_same, 6),
-        "grid_sample_GBps": round(grid_gbs, 1), "render_fwd_alg_GBps": round(fwd_gbs, 1),
+        "grid_sample_GBps": round(grid_gbs, 1),
         "roofline": roof,
+        "rooflines": roofs,
+        "compositing": comp,
     }
 
     if not args.no_semantic:
+        result["mapping_scale"] = mapping_scale(xgs, synth, dev)
         result["semantic_phase"] = semantic_phase(xgs, synth, dev, G)
         result["tracking_and_targets"] = tracking_and_targets(xgs, g, p, b, cams[args.warmup + args.steps - 1], out,
                                                               fT, nl, d_out, grads, bwd_ws, dev)
@@ -268,8 +269,120 @@ def main():
     # ------------------------------------------------------------ CPU baseline
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, synth)
-        result["vq_index_agreement_fp64"] = vq_agreement(*vq_sample)
+        agree, vq_cpu = vq_agreement(*vq_sample)
+        result["vq_index_agreement_fp64"] = agree
+        result["cpu_baseline"].update(vq_cpu)
     print(json.dumps(result), flush=True)
+
+
+SRC = {"render_fwd_mfma_kernel": ["render_fwd.hip", "render_common.h", "common.h"],
+       "render_bwd_mfma_kernel": ["render_bwd.hip", "render_common.h", "common.h", "wave.h"]}
+
+
+def compositing_work(xgs, g, p, b, cam, out, fT, nl, c_sem, m_inst, fwd_ms, bwd_ms):
+    """Algorithmic work of the compositing calls on the last timed frame,
+    counted outside the timed region from the forward's own outputs.
+
+    M = (Gaussian, tile) instances.  E = pixel-Gaussian evaluations a walk
+    needs: each pixel's list positions up to and including its last blended
+    Gaussian (sum of n_last); E_list = the positions of every pixel's whole
+    tile list (the work of a walk without early termination).
+    Bytes (a3): per instance its list entry (4), splat record (32), colour
+    (12) and features (4 c_sem); per pixel C + 2 outputs.  Bytes (a4): the
+    instance reads again, per instance one gradient row (2 + 3 + 1 + 3 + 1 +
+    c_sem floats), per pixel d_out, final_T and n_last, and per Gaussian the
+    projection backward (11 parameter and 3 + 3 + 4 + 1 + 3 + c_sem gradient
+    floats).  ALU: E (20 + C) FP32 lane operations forward and E (35 + 2 C)
+    backward (recompute alpha, recover T, g.c, d alpha, the chain to conic,
+    mean and opacity, w g), against VALU_PEAK_TOPS."""
+    import torch
+    xgs.xgs_render_fwd(g, p, b, cam, out=out, final_T=fT, n_last=nl)
+    _, _, ty, tx = xgs.grid_dims(cam)
+    torch.cuda.synchronize()
+    C = 4 + c_sem
+    hs, ws = nl.shape
+    E = int(nl.to(torch.int64).sum().item())
+    r = b.ranges.to(torch.int64)
+    lens = (r[:, 1] - r[:, 0]).reshape(ty, tx)
+    px = torch.ones((hs, ws), dtype=torch.int64, device=nl.device)
+    per_tile = torch.nn.functional.pad(px, (0, tx * 16 - ws, 0, ty * 16 - hs)).reshape(ty, 16, tx, 16).sum((1, 3))
+    E_list = int((lens * per_tile).sum().item())
+    n = g.n
+    inst_b = 4 + 32 + 12 + 4 * c_sem
+    fwd_bytes = m_inst * inst_b + hs * ws * 4 * (C + 2)
+    bwd_bytes = (m_inst * (inst_b + 4 * (10 + c_sem)) + hs * ws * 4 * (C + 2)
+                 + n * 4 * (11 + 14 + c_sem))
+    fwd_ops, bwd_ops = E * (20 + C), E * (35 + 2 * C)
+
+    def roof(kernel, nbytes, ops, t_ms, what):
+        gbs = nbytes / (t_ms * 1e-3) / 1e9
+        tops = ops / (t_ms * 1e-3) / 1e12
+        hbm, alu = gbs / HBM_PEAK_GBS, tops / VALU_PEAK_TOPS
+        return {"kernel": kernel, "bound": "hbm" if hbm >= alu else "alu",
+                "achieved": round(gbs, 1) if hbm >= alu else round(tops, 2),
+                "peak": HBM_PEAK_GBS if hbm >= alu else round(VALU_PEAK_TOPS, 2),
+                "unit": "GB/s" if hbm >= alu else "Tops/s", "frac": round(max(hbm, alu), 4),
+                "hbm_GBps": round(gbs, 1), "hbm_frac": round(hbm, 4), "alu_Tops": round(tops, 2),
+                "alu_frac": round(alu, 4), "traffic": traffic_for(kernel + "<32", SRC[kernel], nbytes),
+                "algorithmic": what, "ms": t_ms}
+
+    return {
+        "instances_M": m_inst, "evaluations_E": E, "evaluations_E_list": E_list,
+        "mean_walk_per_pixel": round(E / (hs * ws), 1),
+        "fwd_bytes": fwd_bytes, "bwd_bytes": bwd_bytes, "fwd_ops": fwd_ops, "bwd_ops": bwd_ops,
+        "valu_peak_Tops": round(VALU_PEAK_TOPS, 2),
+        "roofline_fwd": roof("render_fwd_mfma_kernel", fwd_bytes, fwd_ops, fwd_ms,
+                             f"M*{inst_b} + px*4*(C+2) = {fwd_bytes:.3e} B; E*(20+C) = {fwd_ops:.3e} ops"),
+        "roofline_bwd": roof("render_bwd_mfma_kernel", bwd_bytes, bwd_ops, bwd_ms,
+                             f"M*({inst_b}+4*(10+c_sem)) + px*4*(C+2) + N*4*(25+c_sem) = {bwd_bytes:.3e} B; "
+                             f"E*(35+2C) = {bwd_ops:.3e} ops; time of the whole xgs_render_bwd call "
+                             "(gradient fill, pixel kernel, projection backward)"),
+    }
+
+
+def mapping_scale(xgs, synth, dev, frames: int = 20, warm: int = 3):
+    """Mapping-scale configuration: 300k-Gaussian room, 640x480, f = 525, 16
+    semantic channels; project -> tile sort -> forward -> backward per frame
+    over 20 poses of the trajectory (after 3 warm-up frames)."""
+    import torch
+    log("mapping scale: 300k room, 640x480, 16 semantic channels")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    scene = synth.room_scene(300_000, seed=2, c_sem=16)
+    g = xgs.Gaussians(t(scene.means), t(scene.log_scales), t(scene.quats), t(scene.opacity), t(scene.colors),
+                      t(scene.features))
+    poses = synth.room_trajectory(100, seed=10)
+    cams = [xgs.camera_from(synth.room_camera(640, 480, 525.0, poses[k])) for k in range(warm + frames)]
+    p = xgs.Projected.alloc(g.n, dev)
+    mmax = 0
+    for c in cams:
+        xgs.xgs_project(g, c, out=p)
+        mmax = max(mmax, int(p.tiles_touched.to(torch.int64).sum().item()))
+    b = xgs.alloc_binning(g.n, int(mmax * 1.25) + 1024, cams[0], dev)
+    C = 20
+    out = torch.empty((C, 480, 640), device=dev)
+    fT = torch.empty((480, 640), device=dev)
+    nl = torch.empty((480, 640), dtype=torch.int32, device=dev)
+    d_out = t(synth.upstream_grad(C, 480, 640, seed=1))
+    grads = xgs.Gaussians.empty_like(g)
+    bws = torch.empty(int(xgs.lib.xgs_render_bwd_workspace(g.n)), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cams]
+    for c, (e0, e1) in zip(cams, evs):
+        e0.record(stream)
+        xgs.xgs_project(g, c, out=p)
+        xgs.xgs_tile_sort(p, c, g.n, b)
+        xgs.xgs_render_fwd(g, p, b, c, out=out, final_T=fT, n_last=nl)
+        xgs.xgs_render_bwd(g, p, b, c, d_out, fT, nl, grads=grads, workspace=bws)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    if int(b.status.item()) != 0:
+        raise RuntimeError("binning capacity exceeded in the mapping-scale leg")
+    f = [e0.elapsed_time(e1) for e0, e1 in evs[warm:]]
+    return {"workload": "300k-Gaussian synthetic room, 640x480, 3+1+16 channels, fwd+bwd per frame over 20 "
+                        "trajectory poses", "frames": frames, "ms_per_frame_mean": round(float(np.mean(f)), 4),
+            "ms_per_frame_median": round(float(np.median(f)), 4),
+            "ms_per_frame_p10": round(float(np.percentile(f, 10)), 4),
+            "ms_per_frame_p90": round(float(np.percentile(f, 90)), 4)}
 
 
 def semantic_phase(xgs, synth, dev, G, reps: int = 10):
@@ -456,46 +569,95 @@ def vq_agreement(Xs, Es, idx_bf16, idx_fp32):
     """Index agreement of the BF16 + rescore and the FP32 plain assignments
     with the FP64 oracle (brute force) on a seeded row sample; tie-adjusted
     counts rows whose two best FP64 distances are within 1e-6 relative as
-    agreeing."""
+    agreeing.  The oracle's assignment of the sample is also the CPU
+    baseline's VQ term: timed with every thread, and on one thread over the
+    first 512 rows, as FP32 bytes of X consumed per second."""
     import oracle
 
+    threads = oracle.set_threads(0)
+    t0 = time.perf_counter()
     ri, d1, d2 = oracle.vq_assign(Xs, Es)
+    t_all = time.perf_counter() - t0
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.vq_assign(Xs[:512], Es)
+    t_one = time.perf_counter() - t0
+    oracle.set_threads(threads)
     tie = (d2 - d1) <= 1e-6 * np.maximum(d1, 1e-30)
     agree = lambda a: (round(float((a == ri).mean()), 6), round(float(((a == ri) | tie).mean()), 6))
     b_raw, b_adj = agree(idx_bf16)
     f_raw, f_adj = agree(idx_fp32)
-    return {"rows": int(len(ri)), "bf16_rescore": b_raw, "bf16_rescore_tie_adjusted": b_adj, "fp32_plain": f_raw,
-            "fp32_plain_tie_adjusted": f_adj}
+    row_b = Xs.shape[1] * 4
+    return ({"rows": int(len(ri)), "bf16_rescore": b_raw, "bf16_rescore_tie_adjusted": b_adj, "fp32_plain": f_raw,
+             "fp32_plain_tie_adjusted": f_adj},
+            {"vq_assign_GBps": round(len(ri) * row_b / t_all / 1e9, 5),
+             "vq_assign_GBps_one_thread": round(512 * row_b / t_one / 1e9, 6),
+             "vq_sample": f"FP64 brute force of {len(ri)} rows x K = {Es.shape[0]}, D = {Xs.shape[1]} "
+                          f"({t_all:.1f} s on {threads} threads; 512 rows on one thread {t_one:.1f} s)"})
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(scene, synth):
-    """The FP64 oracle (single-threaded C) on one frame of the same workload:
-    projection and binning of all 1M Gaussians, compositing forward + backward
-    on every 3rd row of tiles; the compositing time is scaled by the tile
-    fraction to a whole frame."""
+    """The FP64 oracle on one frame of the same workload (1M-Gaussian room,
+    1200x680, 36 channels, the bench's first pose).  All threads: projection,
+    binning, forward and backward compositing of the whole frame and the
+    projection backward.  One thread: the per-Gaussian parts (projection,
+    binning, channels, projection backward) timed whole, the compositing
+    walks on every 3rd row of tiles and scaled by the tile fraction."""
     import oracle
 
     cam = synth.room_camera(1200, 680, 600.0, synth.room_trajectory(100, seed=10)[5])
     hs, ws, ty, tx = oracle.grid_info(cam)
+    g = synth.upstream_grad(4 + scene.c_sem, hs, ws, seed=1).astype(np.float64)
+
+    def frame(tile_mask):
+        ts = {}
+        t0 = time.perf_counter()
+        pr = oracle.project(scene, cam)
+        keys, order, ranges = oracle.bin_instances(pr.rect, oracle.depth_bits(pr.depth), tx, ty)
+        chan = oracle.channels(scene, pr.depth)
+        t1 = time.perf_counter()
+        out, fT, nl, amb = oracle.composite_fwd(pr, scene.opacity, chan, order, ranges, cam, tile_mask)
+        r = oracle.Render(pr, keys, order, ranges, out, fT, nl, amb, chan)
+        d_m2, d_co, d_op, d_ch = oracle.composite_bwd(scene, cam, g, r, tile_mask)
+        t2 = time.perf_counter()
+        oracle.project_bwd(scene, cam, d_m2, d_co, np.ascontiguousarray(d_ch[:, 3]))
+        t3 = time.perf_counter()
+        ts["per_gaussian"] = (t1 - t0) + (t3 - t2)
+        ts["walks"] = t2 - t1
+        return ts
+
+    threads = oracle.set_threads(0)
+    log(f"cpu baseline: oracle frame on {threads} threads")
+    a = frame(None)
+    all_ms = (a["per_gaussian"] + a["walks"]) * 1e3
+    oracle.set_threads(1)
+    log("cpu baseline: oracle frame sample on one thread")
     mask = np.zeros((ty, tx), np.uint8)
     mask[::3] = 1
-    frac = mask.mean()
-    g = synth.upstream_grad(4 + scene.c_sem, hs, ws, seed=1).astype(np.float64)
-    t0 = time.perf_counter()
-    pr = oracle.project(scene, cam)
-    keys, order, ranges = oracle.bin_instances(pr.rect, oracle.depth_bits(pr.depth), tx, ty)
-    t1 = time.perf_counter()
-    chan = oracle.channels(scene, pr.depth)
-    out, fT, nl, amb = oracle.composite_fwd(pr, scene.opacity, chan, order, ranges, cam, mask.ravel())
-    r = oracle.Render(pr, keys, order, ranges, out, fT, nl, amb, chan)
-    oracle.render_grad(scene, cam, g, r, tile_mask=mask.ravel())
-    t2 = time.perf_counter()
-    # render_grad includes the projection backward of all Gaussians once
-    frame_s = (t1 - t0) + (t2 - t1) / frac
-    return {"value": round(frame_s * 1e3, 1), "unit": "ms/frame", "cores": 1, "kind": "oracle",
-            "sample": f"one 1200x680 frame of the 1M-Gaussian room: projection + binning of all Gaussians "
-                      f"({t1 - t0:.1f} s) and forward+backward compositing of every 3rd tile row "
-                      f"({frac:.3f} of the tiles, {t2 - t1:.1f} s) scaled to the full frame"}
+    frac = float(mask.mean())
+    o = frame(mask.ravel())
+    oracle.set_threads(threads)
+    one_ms = (o["per_gaussian"] + o["walks"] / frac) * 1e3
+    return {"value": round(all_ms, 1), "unit": "ms/frame", "cores": threads, "kind": "oracle",
+            "sample": f"one whole 1200x680 frame of the 1M-Gaussian room (fwd+bwd, FP64 C with OpenMP over grid "
+                      f"rows on {threads} threads: per-Gaussian parts {a['per_gaussian']:.2f} s, compositing "
+                      f"walks {a['walks']:.2f} s)",
+            "cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
+            "one_thread_ms_per_frame": round(one_ms, 1),
+            "one_thread_sample": f"per-Gaussian parts of the whole frame ({o['per_gaussian']:.2f} s, unscaled) + "
+                                 f"the walks of every 3rd tile row ({frac:.3f} of the tiles, {o['walks']:.2f} s) "
+                                 f"scaled to the frame"}
 
 
 if __name__ == "__main__":

@@ -258,10 +258,9 @@ class Grads:
     conic: np.ndarray
 
 
-def render_grad(scene, cam, g, r: Render | None = None, tile_mask=None) -> Grads:
-    """Analytic FP64 gradient of L = sum g * out for every parameter group."""
-    if r is None:
-        r = render(scene, cam, tile_mask)
+def composite_bwd(scene, cam, g, r: Render, tile_mask=None):
+    """Gradient of L = sum g * out with respect to the 2D splat parameters and
+    the channels: (d_mean2d [n][2], d_conic [n][3], d_opacity [n], d_chan [n][C])."""
     n = scene.n
     C = r.chan.shape[1]
     d_m2 = np.zeros((n, 2)); d_co = np.zeros((n, 3)); d_op = np.zeros(n); d_ch = np.zeros((n, C))
@@ -271,11 +270,16 @@ def render_grad(scene, cam, g, r: Render | None = None, tile_mask=None) -> Grads
                             _p(np.ascontiguousarray(r.order, np.uint32)),
                             _p(np.ascontiguousarray(r.ranges, np.uint32)), _p(cam_array(cam)),
                             _p(_f64(g)), _p(tm), _p(d_m2), _p(d_co), _p(d_op), _p(d_ch))
-    d_means = np.zeros((n, 3)); d_ls = np.zeros((n, 3)); d_q = np.zeros((n, 4))
-    lib().orc_project_bwd(ctypes.c_int64(n), _p(_f64(scene.means)), _p(_f64(scene.log_scales)),
-                          _p(_f64(scene.quats)), _p(_f64(scene.opacity)), _p(cam_array(cam)),
-                          _p(d_m2), _p(d_co), _p(np.ascontiguousarray(d_ch[:, 3])), _p(d_means),
-                          _p(d_ls), _p(d_q))
+    return d_m2, d_co, d_op, d_ch
+
+
+def render_grad(scene, cam, g, r: Render | None = None, tile_mask=None) -> Grads:
+    """Analytic FP64 gradient of L = sum g * out for every parameter group:
+    the compositing backward, then the projection backward of every Gaussian."""
+    if r is None:
+        r = render(scene, cam, tile_mask)
+    d_m2, d_co, d_op, d_ch = composite_bwd(scene, cam, g, r, tile_mask)
+    d_means, d_ls, d_q = project_bwd(scene, cam, d_m2, d_co, np.ascontiguousarray(d_ch[:, 3]))
     return Grads(d_means, d_ls, d_q, d_op, d_ch[:, :3].copy(), d_ch[:, 4:].copy(), d_m2, d_co)
 
 
