@@ -8,7 +8,9 @@
  *   - All array arguments are DEVICE pointers unless stated otherwise.  The
  *     caller owns every buffer; the library never allocates device memory and
  *     keeps no mutable global state.  Scratch space is passed in as a
- *     workspace whose size comes from the matching *_workspace() query.
+ *     workspace whose size comes from the matching *_workspace() query.  The
+ *     one exception is xgs_tile_sort_noalloc, which uses a fixed scratch
+ *     array the library holds on each GPU.
  *   - Every call is asynchronous and ordered on the hipStream_t passed in
  *     (NULL = the legacy default stream).  No call synchronises the host, so
  *     every call may be captured into a HIP graph.
@@ -206,7 +208,12 @@ xgs_status xgs_render_fwd(const xgs_gaussians* g, const xgs_projected* p, const 
                           xgs_stream_t stream);
 
 /* ------------------------------------------------- a4: render backward
- * Gradient of L = sum d_out * out with respect to every parameter group.  Per
+ * Gradient of L = sum d_out * out with respect to every parameter group: the
+ * derivative of Eq. (rendering) (front-to-back blending, App. B Eq.
+ * (discrete_render)) with respect to alpha, colour, depth and features,
+ * carried through alpha = min(0.99, o G) to opacity, conic and mean2d, then
+ * back through the EWA projection of App. A (Sigma' = J W Sigma W^T J^T,
+ * Sigma = R S S^T R^T) to mean, log-scale and quaternion.  Per
  * pixel the walk runs back to front from n_last, recovering the transmittance
  * before each Gaussian as T / (1 - alpha) from final_T (nothing per pair is
  * stored); dL/dalpha_k = T_k (g . c_k) - S_k / (1 - alpha_k).  Per-Gaussian
@@ -222,6 +229,63 @@ xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected* p, const 
                           const xgs_camera* cam, const float* d_out, const float* final_T,
                           const int32_t* n_last, int32_t flags, xgs_gaussians_grad* grads,
                           void* ws, size_t ws_bytes, xgs_stream_t stream);
+
+/* ------------------------------------------- S3: batched render requests
+ * The serving form renders several requests (scene, pose, resolution) in one
+ * set of launches, each request a "slot".  Slot s owns a band of rows of a
+ * virtual tile grid tiles_x tiles wide: its tile (x, y) is global tile
+ * (row_base + y) * tiles_x + x, so one tile sort over the concatenated
+ * projections, keyed by (global tile, depth) = (slot, tile, depth), gives
+ * every slot's per-tile lists, and one compositing launch takes the tiles of
+ * all slots.  Slot s's Gaussians take global indices [gauss_base, gauss_base
+ * + g.n) in the batch's projected buffers.  Each slot renders exactly what
+ * xgs_project + xgs_tile_sort + xgs_render_fwd give for it alone (same
+ * arithmetic, same per-tile order), whatever else is in the batch.
+ *
+ * The slot table lives in DEVICE memory (n_slots entries), so a HIP graph of
+ * the three calls replays for any batch that fits the capacities it was
+ * captured with: the caller rewrites the table before each replay.  Launch
+ * grids cover the capacities (cap_gaussians, tiles_x * tile_rows); work past
+ * the table's content exits at once.  The table's contents cannot be checked
+ * on the host: xgs_batch_check validates a host copy of it against the
+ * capacities (call it before uploading).  Requirements per slot: 0 <= g.n,
+ * gauss_base + g.n <= next slot's gauss_base (slots ascending, disjoint) and
+ * the last slot's end <= cap_gaussians; the camera is valid with
+ * tiles_x(cam) <= tiles_x; row_base ascending with bands [row_base, row_base
+ * + tiles_y(cam)) disjoint and inside [0, tile_rows); g.c_sem equal to the
+ * c_sem argument; out [4 + c_sem][H_s][W_s], final_T and n_last [H_s][W_s]
+ * of the slot's grid. */
+typedef struct xgs_batch_slot {
+    xgs_gaussians g;     /* the slot's scene (device pointers), g.n Gaussians */
+    xgs_camera cam;      /* the request's camera (viewmat = its pose)         */
+    float* out;          /* [4 + c_sem][H_s][W_s]                             */
+    float* final_T;      /* [H_s][W_s]                                        */
+    int32_t* n_last;     /* [H_s][W_s]                                        */
+    int64_t gauss_base;  /* first global Gaussian index of the slot           */
+    int32_t row_base;    /* first row of the slot's band in the tile grid     */
+    int32_t reserved;
+} xgs_batch_slot;
+enum { XGS_BATCH_MAX_SLOTS = 16 };
+
+/* Validates a HOST copy of a slot table (see above). */
+xgs_status xgs_batch_check(const xgs_batch_slot* h_slots, int32_t n_slots, int64_t cap_gaussians,
+                           int32_t tiles_x, int32_t tile_rows, int32_t c_sem);
+/* a1 over the batch: projects every slot's Gaussians with its camera into
+ * global rows [gauss_base, gauss_base + n) of out (cap_gaussians rows), tile
+ * rectangles in the slot's band of the virtual grid; rows that belong to no
+ * slot get tiles_touched = 0.  The batch is then sorted by xgs_tile_sort (or
+ * xgs_tile_sort_noalloc) with n = cap_gaussians and a camera whose grid is
+ * tiles_x x tile_rows tiles (width 16 tiles_x, height 16 tile_rows, stride
+ * 1): the depth keys and rectangles are all it reads. */
+xgs_status xgs_batch_project(const xgs_batch_slot* d_slots, int32_t n_slots, int64_t cap_gaussians,
+                             int32_t tiles_x, int32_t tile_rows, xgs_projected* out, xgs_stream_t stream);
+/* a3 over the batch: every slot's tiles composited into its own out, final_T
+ * and n_last, exactly as xgs_render_fwd does for one request.  b comes from
+ * the batch tile sort; c_sem is every slot's channel count (0-4, 8, 16 or
+ * 32).  b->tile_order may order the virtual grid's tiles as for one request. */
+xgs_status xgs_batch_render_fwd(const xgs_batch_slot* d_slots, int32_t n_slots, int32_t c_sem,
+                                int32_t tiles_x, int32_t tile_rows, const xgs_projected* p,
+                                const xgs_binning* b, xgs_stream_t stream);
 
 /* -------------------------------------------------- a5: grid-sampled targets
  * App. D, Eq. (target_continuous): for grid pixel (m, n) at image pixel

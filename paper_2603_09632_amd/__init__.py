@@ -19,7 +19,7 @@ from typing import Optional
 import torch
 
 from . import _lib
-from ._lib import XgsBinning, XgsCamera, XgsError, XgsGaussians, XgsProjected, check
+from ._lib import XgsBatchSlot, XgsBinning, XgsCamera, XgsError, XgsGaussians, XgsProjected, check
 
 lib = _lib.load()
 
@@ -37,7 +37,8 @@ __all__ = [
     "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_stage", "xgs_vq_candidates", "xgs_vq_rescore",
     "vq_assign_workspace", "xgs_vq_ema_update", "xgs_semantic_softmax", "xgs_semantic_softmax_bwd",
     "xgs_semantic_loss", "semantic_step", "xgs_pose_grad", "xgs_tracking_loss", "tracking_step", "xgs_region_targets",
-    "xgs_occluder_mask", "xgs_vq_assign_conf", "xgs_vq_ema_update_robust", "render",
+    "xgs_occluder_mask", "xgs_vq_assign_conf", "xgs_vq_ema_update_robust", "render", "BatchLayout",
+    "batch_layout", "batch_table", "xgs_batch_check", "xgs_batch_project", "xgs_batch_render_fwd", "render_batch",
 ]
 
 
@@ -209,6 +210,105 @@ def xgs_tile_sort_noalloc(p: Projected, cam, n: int, b: Binning, stream=None) ->
     check(lib.xgs_tile_sort_noalloc(ctypes.byref(ps), ctypes.byref(c), int(n), ctypes.byref(bs), _stream(stream)),
           "xgs_tile_sort_noalloc")
     return b
+
+
+# ---------------------------------------------------------------- batches
+@dataclass
+class BatchLayout:
+    """Where each request of a batch sits: Gaussian rows and tile-grid band."""
+    tiles_x: int           # width of the virtual tile grid
+    tile_rows: int         # rows of the virtual grid (capacity)
+    cap_gaussians: int     # Gaussian rows of the batch buffers (capacity)
+    gauss_base: list       # first global Gaussian row per slot
+    row_base: list         # first tile row per slot
+
+    def sort_camera(self) -> XgsCamera:
+        """Camera whose grid is the virtual tile grid (for xgs_tile_sort)."""
+        return camera(16 * self.tiles_x, 16 * self.tile_rows, 1.0, 1.0, 0.0, 0.0)
+
+    @property
+    def tiles(self) -> int:
+        return self.tiles_x * self.tile_rows
+
+
+def batch_layout(ns, cams, tiles_x: int, tile_rows: int, cap_gaussians: int) -> BatchLayout:
+    """Packs requests with ns[i] Gaussians and cameras cams[i] into ascending
+    Gaussian rows and tile-row bands; raises XgsError when they do not fit."""
+    gb, rb, g0, r0 = [], [], 0, 0
+    for n, c in zip(ns, cams):
+        _, _, ty, tx = grid_dims(c)
+        if tx > tiles_x:
+            raise XgsError(f"a request is {tx} tiles wide, the batch grid {tiles_x}")
+        gb.append(g0)
+        rb.append(r0)
+        g0 += int(n)
+        r0 += ty
+    if g0 > cap_gaussians or r0 > tile_rows:
+        raise XgsError(f"batch needs {g0} Gaussian rows and {r0} tile rows, capacity {cap_gaussians} / {tile_rows}")
+    return BatchLayout(tiles_x, tile_rows, cap_gaussians, gb, rb)
+
+
+def batch_table(items, layout: BatchLayout):
+    """Host slot table (ctypes array) for items = [(Gaussians, camera, out,
+    final_T, n_last)] in layout's places."""
+    arr = (XgsBatchSlot * max(len(items), 1))()
+    for k, (g, cam, out, fT, nl) in enumerate(items):
+        e = arr[k]
+        e.g = g.struct()
+        e.cam = camera_from(cam)
+        e.out, e.final_T, e.n_last = _ptr(out), _ptr(fT), _ptr(nl)
+        e.gauss_base = layout.gauss_base[k]
+        e.row_base = layout.row_base[k]
+    return arr
+
+
+def xgs_batch_check(table, n_slots: int, layout: BatchLayout, c_sem: int):
+    check(lib.xgs_batch_check(table, int(n_slots), layout.cap_gaussians, layout.tiles_x, layout.tile_rows,
+                              int(c_sem)), "xgs_batch_check")
+
+
+def xgs_batch_project(d_table: torch.Tensor, n_slots: int, layout: BatchLayout, out: Projected, stream=None):
+    ps = out.struct()
+    check(lib.xgs_batch_project(_ptr(d_table), int(n_slots), layout.cap_gaussians, layout.tiles_x, layout.tile_rows,
+                                ctypes.byref(ps), _stream(stream)), "xgs_batch_project")
+    return out
+
+
+def xgs_batch_render_fwd(d_table: torch.Tensor, n_slots: int, c_sem: int, layout: BatchLayout, p: Projected,
+                         b: Binning, stream=None):
+    ps, bs = p.struct(), b.struct()
+    check(lib.xgs_batch_render_fwd(_ptr(d_table), int(n_slots), int(c_sem), layout.tiles_x, layout.tile_rows,
+                                   ctypes.byref(ps), ctypes.byref(bs), _stream(stream)), "xgs_batch_render_fwd")
+
+
+def render_batch(requests, tiles_x: int = 75, tile_rows: Optional[int] = None, cap_gaussians: Optional[int] = None,
+                 max_instances: Optional[int] = None, stream=None):
+    """Renders requests = [(Gaussians, camera)] in one batch (project, tile
+    sort and forward each one launch sequence for all of them).  Returns
+    ([(out, final_T, n_last)], Binning)."""
+    cams = [camera_from(c) for _, c in requests]
+    ns = [g.n for g, _ in requests]
+    rows = sum(grid_dims(c)[2] for c in cams)
+    layout = batch_layout(ns, cams, tiles_x, tile_rows or max(rows, 1), cap_gaussians or max(sum(ns), 1))
+    dev = requests[0][0].means.device
+    c_sem = requests[0][0].c_sem
+    outs = []
+    for g, c in zip((g for g, _ in requests), cams):
+        hs, ws, _, _ = grid_dims(c)
+        outs.append((torch.empty((4 + c_sem, hs, ws), device=dev), torch.empty((hs, ws), device=dev),
+                     torch.empty((hs, ws), dtype=torch.int32, device=dev)))
+    table = batch_table([(g, c, *o) for (g, _), c, o in zip(requests, cams, outs)], layout)
+    xgs_batch_check(table, len(requests), layout, c_sem)
+    d_table = torch.frombuffer(bytearray(bytes(table)), dtype=torch.uint8).to(dev)
+    p = Projected.alloc(layout.cap_gaussians, dev)
+    xgs_batch_project(d_table, len(requests), layout, p, stream=stream)
+    if max_instances is None:
+        max_instances = int(p.tiles_touched.to(torch.int64).sum().item())
+    scam = layout.sort_camera()
+    b = alloc_binning(layout.cap_gaussians, max(max_instances, 1), scam, dev)
+    xgs_tile_sort(p, scam, layout.cap_gaussians, b, stream=stream)
+    xgs_batch_render_fwd(d_table, len(requests), c_sem, layout, p, b, stream=stream)
+    return outs, b
 
 
 def xgs_render_fwd(g: Gaussians, p: Projected, b: Binning, cam, out=None, final_T=None, n_last=None,

@@ -46,6 +46,11 @@ class XgsBinning(ctypes.Structure):
                 ("tile_order", c_void_p)]
 
 
+class XgsBatchSlot(ctypes.Structure):
+    _fields_ = [("g", XgsGaussians), ("cam", XgsCamera), ("out", c_void_p), ("final_T", c_void_p),
+                ("n_last", c_void_p), ("gauss_base", c_int64), ("row_base", c_int32), ("reserved", c_int32)]
+
+
 SIGNATURES = {
     "xgs_status_string": (ctypes.c_char_p, [c_int32]),
     "xgs_last_error": (ctypes.c_char_p, []),
@@ -58,6 +63,10 @@ SIGNATURES = {
                                 P(XgsBinning), c_void_p]),
     "xgs_tile_sort_noalloc_max_bytes": (c_size_t, []),
     "xgs_tile_sort_noalloc": (c_int32, [P(XgsProjected), P(XgsCamera), c_int64, P(XgsBinning), c_void_p]),
+    "xgs_batch_check": (c_int32, [P(XgsBatchSlot), c_int32, c_int64, c_int32, c_int32, c_int32]),
+    "xgs_batch_project": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_int32, P(XgsProjected), c_void_p]),
+    "xgs_batch_render_fwd": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, P(XgsProjected),
+                                       P(XgsBinning), c_void_p]),
     "xgs_render_fwd": (c_int32, [P(XgsGaussians), P(XgsProjected), P(XgsBinning), P(XgsCamera),
                                  c_void_p, c_void_p, c_void_p, c_void_p]),
     "xgs_render_bwd_workspace": (c_size_t, [c_int64]),

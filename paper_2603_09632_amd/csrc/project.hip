@@ -12,23 +12,18 @@ struct CamDev {
     int s, oy, ox, hs, ws;
 };
 
-// viewmat (optional): world->camera matrix in device memory, row-major 4x4;
-// when given it replaces the rotation and translation in c.
-__global__ void __launch_bounds__(256) project_kernel(
-    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
-    const float4* __restrict__ quats, const float* __restrict__ opacity, CamDev c,
-    const float* __restrict__ viewmat, float4* __restrict__ splat, int32_t* __restrict__ radius,
-    uint2* __restrict__ tile_rect, uint32_t* __restrict__ touched) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (viewmat) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) c.R[3 * r + k] = viewmat[4 * r + k];
-            c.t[r] = viewmat[4 * r + 3];
-        }
-    }
+// Projection of Gaussian i (input row) into output row o.  row_off shifts the
+// tile rectangle's rows (the batched form places each request in its own band
+// of a shared tile grid; 0 otherwise).  Products and sums are rounded one by
+// one (no contraction into fused multiply-adds): whether the compiler fuses a
+// product depends on where its operands live (kernel arguments or loads),
+// and the single-request and batched kernels must give the same bits.
+__device__ __forceinline__ void project_one(
+    int64_t i, int64_t o_, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const float* __restrict__ opacity, const CamDev& c, uint32_t row_off,
+    float4* __restrict__ splat, int32_t* __restrict__ radius, uint2* __restrict__ tile_rect,
+    uint32_t* __restrict__ touched) {
+#pragma clang fp contract(off)
     const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
     const float o = opacity[i];
     float px = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
@@ -102,7 +97,8 @@ __global__ void __launch_bounds__(256) project_kernel(
             if (ok) {
                 int x0 = (int)nlo / kTile, x1 = (int)nhi / kTile + 1;
                 int y0 = (int)mlo / kTile, y1 = (int)mhi / kTile + 1;
-                rect = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
+                rect = make_uint2((uint32_t)x0 | (((uint32_t)y0 + row_off) << 16),
+                                  (uint32_t)x1 | (((uint32_t)y1 + row_off) << 16));
                 tt = (uint32_t)((x1 - x0) * (y1 - y0));
                 rad = (int32_t)ceilf(fmaxf(ex, ey));
                 if (rad < 1) rad = 1;
@@ -111,11 +107,77 @@ __global__ void __launch_bounds__(256) project_kernel(
             }
         }
     }
-    splat[2 * i] = s0;
-    splat[2 * i + 1] = s1;
-    radius[i] = rad;
-    tile_rect[i] = rect;
-    touched[i] = tt;
+    splat[2 * o_] = s0;
+    splat[2 * o_ + 1] = s1;
+    radius[o_] = rad;
+    tile_rect[o_] = rect;
+    touched[o_] = tt;
+}
+
+// viewmat (optional): world->camera matrix in device memory, row-major 4x4;
+// when given it replaces the rotation and translation in c.
+__global__ void __launch_bounds__(256) project_kernel(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float4* __restrict__ quats, const float* __restrict__ opacity, CamDev c,
+    const float* __restrict__ viewmat, float4* __restrict__ splat, int32_t* __restrict__ radius,
+    uint2* __restrict__ tile_rect, uint32_t* __restrict__ touched) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (viewmat) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) c.R[3 * r + k] = viewmat[4 * r + k];
+            c.t[r] = viewmat[4 * r + 3];
+        }
+    }
+    project_one(i, i, means, log_scales, quats, opacity, c, 0u, splat, radius, tile_rect, touched);
+}
+
+__host__ __device__ inline CamDev cam_dev(const xgs_camera& cam) {
+    CamDev c;
+    c.fx = cam.fx; c.fy = cam.fy; c.cx = cam.cx; c.cy = cam.cy; c.near_ = cam.near_plane;
+    c.limx = kGuard * (0.5f * cam.width) / cam.fx;
+    c.limy = kGuard * (0.5f * cam.height) / cam.fy;
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) c.R[3 * r + k] = cam.viewmat[4 * r + k];
+        c.t[r] = cam.viewmat[4 * r + 3];
+    }
+    c.s = cam.stride; c.oy = cam.off_y; c.ox = cam.off_x;
+    c.hs = (cam.height + cam.stride - 1) / cam.stride;
+    c.ws = (cam.width + cam.stride - 1) / cam.stride;
+    return c;
+}
+
+// Batched projection: row i of the batch belongs to the slot whose
+// [gauss_base, gauss_base + n) holds it (the block's slot bounds are read
+// once into LDS); rows of no slot are written as culled.
+__global__ void __launch_bounds__(256) project_batch_kernel(
+    const xgs_batch_slot* __restrict__ slots, int n_slots, int64_t cap, float4* __restrict__ splat,
+    int32_t* __restrict__ radius, uint2* __restrict__ tile_rect, uint32_t* __restrict__ touched) {
+    __shared__ int64_t s_lo[XGS_BATCH_MAX_SLOTS], s_hi[XGS_BATCH_MAX_SLOTS];
+    if (threadIdx.x < n_slots) {
+        s_lo[threadIdx.x] = slots[threadIdx.x].gauss_base;
+        s_hi[threadIdx.x] = slots[threadIdx.x].gauss_base + slots[threadIdx.x].g.n;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    int s = -1;
+    for (int j = 0; j < n_slots; ++j)
+        if (i >= s_lo[j] && i < s_hi[j]) s = j;
+    if (s < 0) {
+        splat[2 * i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        splat[2 * i + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        radius[i] = 0;
+        tile_rect[i] = make_uint2(0u, 0u);
+        touched[i] = 0u;
+        return;
+    }
+    const xgs_batch_slot& sl = slots[s];
+    const CamDev c = cam_dev(sl.cam);
+    project_one(i - s_lo[s], i, sl.g.means, sl.g.log_scales, reinterpret_cast<const float4*>(sl.g.quats),
+                sl.g.opacity, c, (uint32_t)sl.row_base, splat, radius, tile_rect, touched);
 }
 
 }  // namespace xgs
@@ -138,15 +200,7 @@ static xgs_status project_impl(const xgs_gaussians* g, const xgs_camera* cam, co
     Grid gr = grid_of(*cam);
     if (gr.tx > 65535 || gr.ty > 65535)
         return fail(XGS_ERR_UNSUPPORTED, std::string(name) + ": more than 65535 tiles along an axis");
-    CamDev c;
-    c.fx = cam->fx; c.fy = cam->fy; c.cx = cam->cx; c.cy = cam->cy; c.near_ = cam->near_plane;
-    c.limx = kGuard * (0.5f * cam->width) / cam->fx;
-    c.limy = kGuard * (0.5f * cam->height) / cam->fy;
-    for (int r = 0; r < 3; ++r) {
-        for (int k = 0; k < 3; ++k) c.R[3 * r + k] = cam->viewmat[4 * r + k];
-        c.t[r] = cam->viewmat[4 * r + 3];
-    }
-    c.s = cam->stride; c.oy = cam->off_y; c.ox = cam->off_x; c.hs = gr.hs; c.ws = gr.ws;
+    CamDev c = cam_dev(*cam);
     int64_t blocks = (g->n + 255) / 256;
     hipLaunchKernelGGL(project_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                        g->n, g->means, g->log_scales, reinterpret_cast<const float4*>(g->quats),
@@ -165,4 +219,58 @@ extern "C" xgs_status xgs_project_posed(const xgs_gaussians* g, const xgs_camera
                                         xgs_stream_t stream) {
     if (!d_viewmat) return fail(XGS_ERR_INVALID_ARG, "xgs_project_posed: null device viewmat");
     return project_impl(g, cam, d_viewmat, out, stream, "xgs_project_posed");
+}
+
+extern "C" xgs_status xgs_batch_check(const xgs_batch_slot* h, int32_t n_slots, int64_t cap_gaussians,
+                                      int32_t tiles_x, int32_t tile_rows, int32_t c_sem) {
+    clear_error();
+    if (n_slots < 0 || n_slots > XGS_BATCH_MAX_SLOTS)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_batch_check: n_slots must be in [0, 16]");
+    if (n_slots > 0 && !h) return fail(XGS_ERR_INVALID_ARG, "xgs_batch_check: null slot table");
+    if (cap_gaussians < 0 || tiles_x < 1 || tile_rows < 1 || tiles_x > 65535 || tile_rows > 65535)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_batch_check: bad capacities");
+    int64_t g_end = 0;
+    int32_t r_end = 0;
+    for (int s = 0; s < n_slots; ++s) {
+        const xgs_batch_slot& sl = h[s];
+        const std::string who = "xgs_batch_check: slot " + std::to_string(s);
+        if (xgs_status st = validate_camera(&sl.cam)) return fail(st, who + ": " + xgs_last_error());
+        Grid gr = grid_of(sl.cam);
+        if (sl.g.n < 0 || sl.gauss_base < g_end || sl.gauss_base + sl.g.n > cap_gaussians)
+            return fail(XGS_ERR_INVALID_ARG, who + ": Gaussian rows overlap or exceed cap_gaussians");
+        if (sl.row_base < r_end || (int64_t)sl.row_base + gr.ty > tile_rows || gr.tx > tiles_x)
+            return fail(XGS_ERR_INVALID_ARG, who + ": tile band overlaps or exceeds the grid");
+        if (sl.g.c_sem != c_sem) return fail(XGS_ERR_INVALID_ARG, who + ": c_sem differs");
+        if (!sl.out || !sl.final_T || !sl.n_last) return fail(XGS_ERR_INVALID_ARG, who + ": null output");
+        if (sl.g.n > 0 && (!sl.g.means || !sl.g.log_scales || !sl.g.quats || !sl.g.opacity || !sl.g.colors ||
+                           (c_sem > 0 && !sl.g.features)))
+            return fail(XGS_ERR_INVALID_ARG, who + ": null Gaussian array");
+        if (sl.g.n > 0 && !aligned(sl.g.quats, 16))
+            return fail(XGS_ERR_INVALID_ARG, who + ": quats need 16-byte alignment");
+        g_end = sl.gauss_base + sl.g.n;
+        r_end = sl.row_base + gr.ty;
+    }
+    return XGS_OK;
+}
+
+extern "C" xgs_status xgs_batch_project(const xgs_batch_slot* d_slots, int32_t n_slots, int64_t cap_gaussians,
+                                        int32_t tiles_x, int32_t tile_rows, xgs_projected* out,
+                                        xgs_stream_t stream) {
+    clear_error();
+    if (!out) return fail(XGS_ERR_INVALID_ARG, "xgs_batch_project: null argument");
+    if (n_slots < 0 || n_slots > XGS_BATCH_MAX_SLOTS)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_batch_project: n_slots must be in [0, 16]");
+    if (n_slots > 0 && !d_slots) return fail(XGS_ERR_INVALID_ARG, "xgs_batch_project: null slot table");
+    if (cap_gaussians < 0 || tiles_x < 1 || tile_rows < 1 || tiles_x > 65535 || tile_rows > 65535)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_batch_project: bad capacities");
+    if (cap_gaussians == 0) return XGS_OK;
+    if (!out->splat || !out->radius || !out->tile_rect || !out->tiles_touched)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_batch_project: null output array");
+    if (!aligned(out->splat, 16) || !aligned(out->tile_rect, 8))
+        return fail(XGS_ERR_INVALID_ARG, "xgs_batch_project: splat needs 16-byte, tile_rect 8-byte alignment");
+    const int64_t blocks = (cap_gaussians + 255) / 256;
+    hipLaunchKernelGGL(project_batch_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, d_slots,
+                       (int)n_slots, cap_gaussians, reinterpret_cast<float4*>(out->splat), out->radius,
+                       reinterpret_cast<uint2*>(out->tile_rect), out->tiles_touched);
+    return check_launch("xgs_batch_project");
 }

@@ -36,13 +36,33 @@ struct QuadPix {
     float px, py;
 };
 
+// Slots go round-robin over the eight XCDs (the four quadrants of a slot
+// share one XCD and its L2); the order table maps slot -> tile.
+__device__ __forceinline__ int quad_slot() {
+    const int b = blockIdx.x;
+    return ((b >> 3) >> 2) * 8 + (b & 7);
+}
+__device__ __forceinline__ int quad_index() { return (blockIdx.x >> 3) & 3; }
+
+// Pixel of this lane in quadrant q of tile `tile` of grid g.
+__device__ __forceinline__ QuadPix quad_pixel_at(const TileGrid& g, int tile, int q) {
+    QuadPix r;
+    r.tile = tile;
+    const int lane = threadIdx.x;
+    const int tx = r.tile % g.tx, ty = r.tile / g.tx;
+    r.n = tx * kTile + (q & 1) * 8 + (lane & 7);
+    r.m = ty * kTile + (q >> 1) * 8 + (lane >> 3);
+    r.inside = r.tile < g.tiles && r.n < g.ws && r.m < g.hs;
+    r.px = (float)g.ox + (float)r.n * (float)g.s + 0.5f;
+    r.py = (float)g.oy + (float)r.m * (float)g.s + 0.5f;
+    return r;
+}
+
 __device__ __forceinline__ QuadPix quad_pixel(const TileGrid& g) {
     const int b = blockIdx.x;
     const int xcd = b & 7, k = b >> 3;
     const int q = k & 3;
     QuadPix r;
-    // Slots go round-robin over the eight XCDs (the four quadrants of a slot
-    // share one XCD and its L2); the order table maps slot -> tile.
     const int slot = (k >> 2) * 8 + xcd;
     r.tile = (g.order && slot < g.tiles) ? (int)__builtin_amdgcn_readfirstlane((int)g.order[slot]) : slot;
     const int lane = threadIdx.x;
@@ -142,6 +162,40 @@ __device__ __forceinline__ float channel_of(const float* __restrict__ colors, co
 // indexed by it become scalar (constant-cache) loads.
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Batched requests: the slot of a global tile and the slot's own tile grid.
+// Slot s owns rows [row_base, row_base + tiles_y) of a virtual grid gtx tiles
+// wide; tiles at columns >= the slot's tiles_x are empty.  Returns false when
+// the tile belongs to no slot (or lies past its columns).
+struct BatchTile {
+    int slot, tile;  // slot index, tile index within the slot's grid
+    TileGrid grid;   // the slot's grid (no order table)
+};
+
+__device__ __forceinline__ bool batch_tile(const xgs_batch_slot* __restrict__ slots, int n_slots, int gtx,
+                                           int gtile, BatchTile& bt) {
+    const int grow = gtile / gtx, gcol = gtile - (gtile / gtx) * gtx;
+    for (int j = 0; j < n_slots; ++j) {
+        const xgs_camera& c = slots[j].cam;
+        const int rb = (int)uniform((uint32_t)slots[j].row_base);
+        const int st = (int)uniform((uint32_t)c.stride);
+        const int hs = ((int)uniform((uint32_t)c.height) + st - 1) / st;
+        const int ws = ((int)uniform((uint32_t)c.width) + st - 1) / st;
+        const int ty = (hs + kTile - 1) / kTile, tx = (ws + kTile - 1) / kTile;
+        if (grow >= rb && grow < rb + ty) {
+            if (gcol >= tx) return false;
+            bt.slot = j;
+            bt.tile = (grow - rb) * tx + gcol;
+            bt.grid.hs = hs; bt.grid.ws = ws; bt.grid.tx = tx; bt.grid.ty = ty; bt.grid.tiles = tx * ty;
+            bt.grid.s = st;
+            bt.grid.oy = (int)uniform((uint32_t)c.off_y);
+            bt.grid.ox = (int)uniform((uint32_t)c.off_x);
+            bt.grid.order = nullptr;
+            return true;
+        }
+    }
+    return false;
 }
 
 }  // namespace xgs

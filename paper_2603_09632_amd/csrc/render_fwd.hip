@@ -30,17 +30,49 @@ namespace xgs {
 // register allocation gives (at CS = 32 the kernel fits 4).  For the same
 // reason the per-splat step has no branches and reads its ring record two
 // splats ahead, so those LDS reads overlap the previous splats' chains.
-template <int CS, bool EXACT>
+//
+// BATCH: the tiles of several requests in one launch (serving).  g then
+// describes the virtual grid (tx = its width in tiles, tiles = all of it,
+// order over it); each workgroup finds its request's slot, takes that slot's
+// grid, colours, features and outputs, and reads the tile list of the global
+// tile.  Splat records are indexed by global Gaussian index, colours and
+// features by index within the slot's scene.
+template <int CS, bool EXACT, bool BATCH = false>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) render_fwd_mfma_kernel(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float4* __restrict__ splat, const float* __restrict__ colors,
     const float* __restrict__ features, int csem, TileGrid g, float* __restrict__ out,
-    float* __restrict__ final_T, int32_t* __restrict__ n_last) {
+    float* __restrict__ final_T, int32_t* __restrict__ n_last, const xgs_batch_slot* __restrict__ slots = nullptr,
+    int n_slots = 0) {
     constexpr int CH = 4 + CS;
     constexpr int NT = (CH + 15) / 16;
     __shared__ float wl[64 * 17];
     __shared__ Ring ring;
-    const QuadPix P = quad_pixel(g);
+    QuadPix P;
+    int rtile;  // tile whose list is read (the global tile when batched)
+    if constexpr (BATCH) {
+        const int slot = quad_slot();
+        if (slot >= g.tiles) return;
+        rtile = g.order ? (int)uniform(g.order[slot]) : slot;
+        BatchTile bt;
+        if (!batch_tile(slots, n_slots, g.tx, rtile, bt)) return;
+        const xgs_batch_slot& sl = slots[bt.slot];
+        // colours and features are indexed by global Gaussian index: shift
+        // their bases by the slot's first global index
+        const int64_t base = (int64_t)sl.gauss_base;
+        colors = reinterpret_cast<const float*>(reinterpret_cast<uintptr_t>(sl.g.colors) -
+                                                (uintptr_t)(base * 3 * (int64_t)sizeof(float)));
+        features = reinterpret_cast<const float*>(reinterpret_cast<uintptr_t>(sl.g.features) -
+                                                  (uintptr_t)(base * (EXACT ? CS : csem) * (int64_t)sizeof(float)));
+        out = sl.out;
+        final_T = sl.final_T;
+        n_last = sl.n_last;
+        g = bt.grid;
+        P = quad_pixel_at(g, bt.tile, quad_index());
+    } else {
+        P = quad_pixel(g);
+        rtile = P.tile;
+    }
     if (P.tile >= g.tiles) return;
     const QuadRect qr = quad_rect(g, P);
     const int lane = threadIdx.x;
@@ -52,8 +84,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) re
     float T = 1.f;
     int last = 0;
     bool done = !P.inside;
-    const uint32_t start = uniform(ranges[2 * P.tile]);
-    const int len = (int)(uniform(ranges[2 * P.tile + 1]) - start);
+    const uint32_t start = uniform(ranges[2 * rtile]);
+    const int len = (int)(uniform(ranges[2 * rtile + 1]) - start);
     // candidate registers: list entry and splat record of position cpos + lane
     int cg = -1;
     float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
@@ -172,9 +204,47 @@ static void launch_fwd(const xgs_gaussians* g, const xgs_projected* p, const xgs
                            g->c_sem, tg, out, final_T, n_last);
 }
 
+template <int CS>
+static void launch_fwd_batch(const xgs_batch_slot* slots, int n_slots, const xgs_projected* p,
+                             const xgs_binning* b, const TileGrid& tg, hipStream_t st) {
+    hipLaunchKernelGGL((render_fwd_mfma_kernel<CS, true, true>), dim3(quad_blocks(tg)), dim3(64), 0, st, b->ranges,
+                       b->vals, reinterpret_cast<const float4*>(p->splat), nullptr, nullptr, CS, tg, nullptr,
+                       nullptr, nullptr, slots, n_slots);
+}
+
 }  // namespace xgs
 
 using namespace xgs;
+
+extern "C" xgs_status xgs_batch_render_fwd(const xgs_batch_slot* d_slots, int32_t n_slots, int32_t c_sem,
+                                           int32_t tiles_x, int32_t tile_rows, const xgs_projected* p,
+                                           const xgs_binning* b, xgs_stream_t stream) {
+    clear_error();
+    if (!p || !b) return fail(XGS_ERR_INVALID_ARG, "xgs_batch_render_fwd: null argument");
+    if (n_slots < 0 || n_slots > XGS_BATCH_MAX_SLOTS)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_batch_render_fwd: n_slots must be in [0, 16]");
+    if (n_slots > 0 && !d_slots) return fail(XGS_ERR_INVALID_ARG, "xgs_batch_render_fwd: null slot table");
+    if (tiles_x < 1 || tile_rows < 1 || tiles_x > 65535 || tile_rows > 65535 ||
+        (int64_t)tiles_x * tile_rows >= (int64_t(1) << 31))
+        return fail(XGS_ERR_INVALID_ARG, "xgs_batch_render_fwd: bad tile grid");
+    if (!p->splat || !b->ranges || !b->vals) return fail(XGS_ERR_INVALID_ARG, "xgs_batch_render_fwd: null array");
+    if (!aligned(p->splat, 16)) return fail(XGS_ERR_INVALID_ARG, "xgs_batch_render_fwd: splat must be 16-byte aligned");
+    if (n_slots == 0) return XGS_OK;
+    TileGrid tg;
+    tg.tx = tiles_x; tg.ty = tile_rows; tg.tiles = tiles_x * tile_rows;
+    tg.hs = 16 * tile_rows; tg.ws = 16 * tiles_x; tg.s = 1; tg.oy = 0; tg.ox = 0;
+    tg.order = b->tile_order;
+    hipStream_t st = (hipStream_t)stream;
+    switch (c_sem) {
+#define XGS_BFWD_CASE(n) case n: launch_fwd_batch<n>(d_slots, n_slots, p, b, tg, st); break;
+        XGS_BFWD_CASE(0) XGS_BFWD_CASE(1) XGS_BFWD_CASE(2) XGS_BFWD_CASE(3) XGS_BFWD_CASE(4)
+        XGS_BFWD_CASE(8) XGS_BFWD_CASE(16) XGS_BFWD_CASE(32)
+#undef XGS_BFWD_CASE
+        default:
+            return fail(XGS_ERR_UNSUPPORTED, "xgs_batch_render_fwd: c_sem must be one of 0-4, 8, 16, 32");
+    }
+    return check_launch("xgs_batch_render_fwd");
+}
 
 extern "C" xgs_status xgs_render_fwd(const xgs_gaussians* g, const xgs_projected* p,
                                      const xgs_binning* b, const xgs_camera* cam, float* out,
