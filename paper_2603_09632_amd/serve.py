@@ -1,29 +1,41 @@
 """Serving form: continuous batching of render requests over resident scenes.
 
 Scenes (Gaussian sets) stay resident in HBM.  A request names a scene, a pose
-and a camera of one of the configured resolutions.  The scheduler thread admits
-requests first-come first-served whenever (a) fewer than ``max_inflight`` are
-on the GPU and (b) the scratch they need fits the HBM budget; requests that
-arrive while others run are admitted as soon as both free up, so their work
-overlaps on the device.
+and a camera of one of the configured resolutions.  Requests are rendered in
+batches: a batch is one projection launch, one tile sort and one compositing
+launch for all of its requests (xgs_batch_project, xgs_tile_sort over the
+batch, xgs_batch_render_fwd), each request a slot with its own band of tile
+rows, so the sort is keyed by (slot, tile, depth).
 
-Scratch lives in buffer sets (projection, binning, image) keyed by (scene,
-resolution) and pooled: a finished request returns its set to the pool, and
-the HBM ledger counts every set that exists.  When a new set would exceed the
-budget, free sets are evicted (least recently used); if none is free the
-request waits.  A buffer set runs its first request eagerly and then carries a
-HIP graph of project -> tile sort -> render forward, captured on its second
-use; the pose enters through a 16-float device buffer (xgs_project_posed), so
-a replay serves any pose.  Replays go round-robin to a pool of streams.
+Batches run in arenas: fixed buffers (batch projection, binning, sort
+workspace, slot table) sized once from the HBM budget, with capacities in
+Gaussians, tile rows, instances and slots.  Each arena has its own stream and
+carries HIP graphs of the three calls, one per capacity bucket (Gaussian rows
+and tile rows rounded up to powers of two), each captured on the bucket's
+second batch; a batch rewrites the arena's device slot table (scene
+pointers, pose, output pointers) and replays its bucket's graph, so any mix
+of scenes, poses and resolutions within a bucket replays the same graph, and
+a small batch does not pay for the full capacity.  With two arenas one batch
+is formed and launched while the other runs (continuous batching): requests
+that arrive while a batch is on the GPU go into the next batch as soon as an
+arena frees up, first come first served, as many as fit.
 
-Results are independent of what else is in flight: every kernel of a request
-reads only that request's scene and buffers, per-tile order is deterministic
-and the forward pass uses no atomics, so a request renders bit-identically
-alone and in a mix.
+Admission by memory: the arenas' bytes plus the outputs of the requests in
+flight stay within the budget; a request whose scene does not fit an arena
+fails with MemoryError.  A batch whose instances overflow the binning is
+detected on the device (status), its requests go back to the head of the
+queue with larger per-(scene, resolution) instance estimates, and an arena
+grows when a single request needs more than it holds.
+
+Results are independent of the batch: each slot's tiles hold only its own
+Gaussians, per-tile order is (depth, index) and the forward pass has no
+atomics, so a request renders bit-identically alone, batched, or through the
+single-request calls.
 """
 from __future__ import annotations
 
 import collections
+import ctypes
 import queue
 import threading
 import time
@@ -34,8 +46,11 @@ from typing import Optional
 import numpy as np
 import torch
 
-from . import (Binning, Gaussians, Projected, alloc_binning, camera, grid_dims, xgs_project_posed,
-               xgs_render_fwd, xgs_tile_sort)
+from . import (BatchLayout, Gaussians, Projected, XgsBatchSlot, alloc_binning, batch_table, camera, grid_dims,
+               lib, xgs_batch_check, xgs_batch_project, xgs_batch_render_fwd, xgs_tile_sort)
+
+TILES_X = 75               # virtual grid width: the widest resolution served (1200 px) in tiles
+ORDER_TILES = 16384        # the tile sort orders up to this many tiles longest-first
 
 
 @dataclass(frozen=True)
@@ -66,109 +81,112 @@ class _Request:
     future: Future = field(default_factory=Future)
 
 
-class _BufferSet:
-    """Scratch for one in-flight request of a (scene, resolution) pair."""
+def _bucket(value: int, top: int, first: int) -> int:
+    """Smallest of first, 2 first, 4 first, ... that is >= value, at most top."""
+    b = first
+    while b < value and b < top:
+        b *= 2
+    return min(b, top)
 
-    def __init__(self, server: "Server", scene: str, res: Resolution, cap: int):
-        g = server.scenes[scene]
+
+class _Arena:
+    """Buffers, stream and graphs of one batch in flight.  Launch grids cover
+    a capacity bucket (Gaussian rows and tile rows rounded up to a power-of-two
+    multiple), one graph per bucket, so a small batch does not pay for the
+    arena's full capacity."""
+
+    def __init__(self, server: "Server", cap_gaussians: int, tile_rows: int, max_instances: int):
         dev = server.device
-        self.key = (scene, res)
-        self.cam = camera(res.width, res.height, res.fx, res.fy, res.cx, res.cy, near=server.near)
-        hs, ws, _, _ = grid_dims(self.cam)
-        self.viewmat_host = torch.empty((4, 4), dtype=torch.float32).pin_memory()
-        self.viewmat_dev = torch.zeros((4, 4), dtype=torch.float32, device=dev)
-        self.proj = Projected.alloc(g.n, dev)
-        self.cap = cap
-        self.binning: Binning = alloc_binning(g.n, self.cap, self.cam, dev)
-        self.out = torch.empty((4 + g.c_sem, hs, ws), device=dev)
-        self.final_T = torch.empty((hs, ws), device=dev)
-        self.n_last = torch.empty((hs, ws), dtype=torch.int32, device=dev)
+        self.server = server
+        self.cap_gaussians, self.tile_rows, self.max_instances = cap_gaussians, tile_rows, max_instances
+        self.stream = torch.cuda.Stream(device=dev)
+        self.proj = Projected.alloc(cap_gaussians, dev)
+        full = BatchLayout(TILES_X, tile_rows, cap_gaussians, [], [])
+        self.binning = alloc_binning(cap_gaussians, max_instances, full.sort_camera(), dev)
+        slot_bytes = ctypes.sizeof(XgsBatchSlot)
+        self.h_table = torch.zeros(server.max_slots * slot_bytes, dtype=torch.uint8).pin_memory()
+        self.d_table = torch.zeros(server.max_slots * slot_bytes, dtype=torch.uint8, device=dev)
         self.status_host = torch.zeros(1, dtype=torch.int32).pin_memory()
-        self.graph: Optional[torch.cuda.CUDAGraph] = None
-        self.uses = 0
+        self.graphs: dict = {}
+        self.uses: collections.Counter = collections.Counter()
+        self.batches = 0
+        self.busy = None            # (requests, layout, outputs, event, t_launch, output bytes) while a batch runs
         self.nbytes = sum(t.numel() * t.element_size() for t in (
-            self.viewmat_dev, self.proj.splat, self.proj.radius, self.proj.tile_rect, self.proj.tiles_touched,
-            self.binning.keys, self.binning.vals, self.binning.ranges, self.binning.workspace,
-            self.binning.tile_order, self.out, self.final_T, self.n_last))
-        # The fills above ran on this thread's current stream; the set is used
-        # on the (non-blocking) launch streams, which wait for this event first.
+            self.proj.splat, self.proj.radius, self.proj.tile_rect, self.proj.tiles_touched, self.binning.keys,
+            self.binning.vals, self.binning.ranges, self.binning.workspace, self.binning.tile_order, self.d_table))
         self.ready = torch.cuda.Event()
         self.ready.record()
 
-    def enqueue(self, g: Gaussians):
-        """project -> sort -> render on the current stream (also the body that
-        gets captured)."""
-        xgs_project_posed(g, self.cam, self.viewmat_dev, out=self.proj)
-        xgs_tile_sort(self.proj, self.cam, g.n, self.binning)
-        xgs_render_fwd(g, self.proj, self.binning, self.cam, out=self.out, final_T=self.final_T,
-                       n_last=self.n_last)
+    @staticmethod
+    def bytes_for(cap_gaussians: int, tile_rows: int, max_instances: int, max_slots: int) -> int:
+        tiles = TILES_X * tile_rows
+        ws = int(lib.xgs_tile_sort_workspace(cap_gaussians, max_instances, tiles))
+        return (cap_gaussians * 48 + max_instances * 12 + tiles * 12 + ws + 16
+                + max_slots * ctypes.sizeof(XgsBatchSlot))
+
+    def bucket(self, gaussians: int, rows: int) -> tuple:
+        return (_bucket(gaussians, self.cap_gaussians, 1 << 18), _bucket(rows, self.tile_rows, 32))
+
+    def body(self, key: tuple):
+        """The batch's launches on the current stream (also what is captured)."""
+        s = self.server
+        layout = BatchLayout(TILES_X, key[1], key[0], [], [])
+        xgs_batch_project(self.d_table, s.max_slots, layout, self.proj)
+        xgs_tile_sort(self.proj, layout.sort_camera(), key[0], self.binning)
+        xgs_batch_render_fwd(self.d_table, s.max_slots, s.c_sem, layout, self.proj, self.binning)
 
 
 class Server:
     """Continuous-batching render server.  ``scenes`` maps ids to resident
-    Gaussians; ``submit`` returns a Future of RenderResult."""
+    Gaussians (one semantic channel count for all); ``submit`` returns a
+    Future of RenderResult.  ``max_inflight`` is the number of slots of a
+    batch, ``streams`` the number of arenas (batches in flight)."""
 
     def __init__(self, scenes: dict[str, Gaussians], hbm_budget_bytes: int = 4 << 30, max_inflight: int = 8,
-                 streams: int = 4, use_graphs: bool = True, near: float = 0.2, device=None):
+                 streams: int = 2, use_graphs: bool = True, near: float = 0.2, device=None,
+                 cap_gaussians: Optional[int] = None, max_instances: Optional[int] = None):
         self.device = device or torch.device("cuda")
         self.scenes = scenes
+        c_sems = {g.c_sem for g in scenes.values()}
+        if len(c_sems) != 1:
+            raise ValueError("all served scenes need the same semantic channel count")
+        self.c_sem = c_sems.pop()
         self.budget = int(hbm_budget_bytes)
-        self.max_inflight = int(max_inflight)
+        self.max_slots = max(1, min(int(max_inflight), 16))
         self.use_graphs = use_graphs
         self.near = near
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
-        self._side = torch.cuda.Stream(device=self.device)
-        self._rr = 0
-        self._pool: dict = collections.defaultdict(list)  # key -> free buffer sets
-        self._lru: collections.OrderedDict = collections.OrderedDict()  # free sets, LRU order
+        n_arenas = max(1, int(streams))
+        largest = max(g.n for g in scenes.values())
+        tile_rows = ORDER_TILES // TILES_X
+        # Arena capacities: by default room for about four of the largest
+        # scenes per batch (at most max_slots), within half of the budget;
+        # the other half is for the outputs of the requests in flight.
+        cap = int(cap_gaussians or min(4 * largest, self.max_slots * largest))
+        inst = int(max_instances or 2 * cap)
+        while cap > 1 and n_arenas * _Arena.bytes_for(cap, tile_rows, inst, self.max_slots) > self.budget // 2:
+            cap = cap * 3 // 4
+            inst = inst * 3 // 4
+        self._arena_args = (cap, tile_rows, inst)
+        self._n_arenas = n_arenas
+        self.arenas: list[_Arena] = []
         self.ledger_bytes = 0
         self.peak_ledger_bytes = 0
-        self._capacity: dict = {}
+        self._out_bytes = 0
+        self._est: dict = {}
         self._queue: queue.Queue = queue.Queue()
         self._pending: collections.deque = collections.deque()
-        self._inflight: list = []
         self._rid = 0
         self._lock = threading.Lock()
         self._stop = threading.Event()
-        self.completed: list[RenderResult] = []
+        self.completed: list = []           # (latency_s, queued_s) of each finished request
         self.rejected = 0
         self.overflows = 0
-        self.sets_created = 0
-        self.evictions = 0
+        self.batches = 0
+        self.batched_requests = 0
         self.graphs_captured = 0
+        self.arena_growths = 0
         self._thread = threading.Thread(target=self._loop, name="xgs-serve", daemon=True)
         self._thread.start()
-
-    # ------------------------------------------------------------ capacity
-    def capacity(self, scene: str, res: Resolution) -> int:
-        """Instance capacity of a new buffer set.  Until a (scene, resolution)
-        pair has been measured this is a generous bound (4 instances per
-        Gaussian, at least the tile count), used for admission; the first
-        buffer set of a pair measures the instance count at its request's pose
-        and keeps 1.5x of it.  A later overflow is detected on the device:
-        the capacity grows to 1.25x of what the request needed, the undersized
-        set is discarded and the request goes back to the head of the queue."""
-        key = (scene, res)
-        if key in self._capacity:
-            return self._capacity[key]
-        n = self.scenes[scene].n
-        _, _, ty, tx = grid_dims(camera(res.width, res.height, res.fx, res.fy, res.cx, res.cy))
-        return max(4 * n, ty * tx) + 1024
-
-    def _measure_capacity(self, scene: str, res: Resolution, viewmat: np.ndarray) -> int:
-        key = (scene, res)
-        if key not in self._capacity:
-            g = self.scenes[scene]
-            cam = camera(res.width, res.height, res.fx, res.fy, res.cx, res.cy, near=self.near)
-            # on the side stream: the host waits for this projection only,
-            # not for the replays queued on the launch streams
-            with torch.cuda.stream(self._side):
-                vm = torch.from_numpy(viewmat).to(self.device, non_blocking=False)
-                p = xgs_project_posed(g, cam, vm)
-                m = int(p.tiles_touched.to(torch.int64).sum().item())
-            _, _, ty, tx = grid_dims(cam)
-            self._capacity[key] = max(int(1.5 * m), ty * tx) + 1024
-        return self._capacity[key]
 
     # ----------------------------------------------------------------- api
     def submit(self, scene: str, viewmat, res: Resolution) -> Future:
@@ -189,141 +207,193 @@ class Server:
         self._thread.join()
 
     def stats(self) -> dict:
-        lat = np.array([r.latency_s for r in self.completed]) * 1e3
+        lat = np.array([c[0] for c in self.completed]) * 1e3
         if len(lat) == 0:
             return {"completed": 0}
-        qd = np.array([r.queued_s for r in self.completed]) * 1e3
+        qd = np.array([c[1] for c in self.completed]) * 1e3
         return {"completed": len(lat), "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
                 "p50_queued_ms": float(np.percentile(qd, 50)), "p99_queued_ms": float(np.percentile(qd, 99)),
-                "peak_hbm_scratch_MB": self.peak_ledger_bytes / 2 ** 20, "budget_MB": self.budget / 2 ** 20,
-                "sets_created": self.sets_created, "evictions": self.evictions,
-                "graphs_captured": self.graphs_captured, "overflows": self.overflows}
+                "peak_hbm_MB": self.peak_ledger_bytes / 2 ** 20, "budget_MB": self.budget / 2 ** 20,
+                "batches": self.batches, "mean_batch": self.batched_requests / max(self.batches, 1),
+                "graphs_captured": self.graphs_captured, "overflows": self.overflows,
+                "arena_growths": self.arena_growths}
 
     # ------------------------------------------------------------ internals
-    def _acquire(self, scene: str, res: Resolution, viewmat: np.ndarray) -> Optional[_BufferSet]:
-        key = (scene, res)
-        if self._pool[key]:
-            bs = self._pool[key].pop()
-            self._lru.pop(id(bs), None)
-            return bs
-        need = self._estimate(scene, res)
-        while self.ledger_bytes + need > self.budget and self._lru:
-            _, victim = self._lru.popitem(last=False)
-            self._pool[victim.key].remove(victim)
-            self.ledger_bytes -= victim.nbytes
-            self.evictions += 1
-            del victim
-        if self.ledger_bytes + need > self.budget:
-            return None
-        bs = _BufferSet(self, scene, res, self._measure_capacity(scene, res, viewmat))
-        self.sets_created += 1
-        self.ledger_bytes += bs.nbytes
+    def _cam(self, res: Resolution, viewmat=None):
+        return camera(res.width, res.height, res.fx, res.fy, res.cx, res.cy, viewmat=viewmat, near=self.near)
+
+    def _out_nbytes(self, res: Resolution) -> int:
+        hs, ws, _, _ = grid_dims(self._cam(res))
+        return (4 + self.c_sem) * hs * ws * 4 + hs * ws * 8
+
+    def _estimate(self, req: _Request) -> int:
+        """Instance estimate of a (scene, resolution): 1.5 per Gaussian until
+        an overflow measured more."""
+        return self._est.get((req.scene, req.res), int(1.5 * self.scenes[req.scene].n) + 1024)
+
+    def _charge(self, nbytes: int):
+        self.ledger_bytes += nbytes
         self.peak_ledger_bytes = max(self.peak_ledger_bytes, self.ledger_bytes)
-        return bs
 
-    def _release(self, bs: _BufferSet):
-        self._pool[bs.key].append(bs)
-        self._lru[id(bs)] = bs
+    def _ensure_arenas(self):
+        while len(self.arenas) < self._n_arenas:
+            a = _Arena(self, *self._arena_args)
+            self._charge(a.nbytes)
+            self.arenas.append(a)
 
-    def _estimate(self, scene: str, res: Resolution) -> int:
-        g = self.scenes[scene]
-        cap = self.capacity(scene, res)
-        hs, ws, ty, tx = grid_dims(camera(res.width, res.height, res.fx, res.fy, res.cx, res.cy))
-        from . import lib
-        ws_bytes = int(lib.xgs_tile_sort_workspace(g.n, cap, ty * tx))
-        return (64 + g.n * 48 + cap * 12 + ty * tx * 12 + 16 + ws_bytes + (4 + g.c_sem) * hs * ws * 4
-                + hs * ws * 8)
+    def _form_batch(self, arena: _Arena) -> list:
+        """Pending requests that fit the arena together, in arrival order."""
+        batch, g_used, rows, inst, out_b = [], 0, 0, 0, 0
+        while self._pending and len(batch) < self.max_slots:
+            req = self._pending[0]
+            n = self.scenes[req.scene].n
+            _, _, ty, tx = grid_dims(self._cam(req.res))
+            if n > arena.cap_gaussians or ty > arena.tile_rows or tx > TILES_X:
+                self._pending.popleft()
+                self.rejected += 1
+                req.future.set_exception(MemoryError("request does not fit a batch arena within the HBM budget"))
+                continue
+            est, ob = self._estimate(req), self._out_nbytes(req.res)
+            if batch and (g_used + n > arena.cap_gaussians or rows + ty > arena.tile_rows
+                          or inst + est > arena.max_instances):
+                break
+            if self.ledger_bytes + self._out_bytes + out_b + ob > self.budget:
+                if not batch and not any(a.busy for a in self.arenas):
+                    self._pending.popleft()
+                    self.rejected += 1
+                    req.future.set_exception(MemoryError("request output exceeds the HBM budget"))
+                    continue
+                break
+            batch.append(self._pending.popleft())
+            g_used, rows, inst, out_b = g_used + n, rows + ty, inst + est, out_b + ob
+        return batch
 
-    def _launch(self, req: _Request, bs: _BufferSet):
-        g = self.scenes[req.scene]
-        s = self.streams[self._rr % len(self.streams)]
-        self._rr += 1
-        bs.viewmat_host.copy_(torch.from_numpy(req.viewmat))
-        with torch.cuda.stream(s):
-            s.wait_event(bs.ready)
-            bs.viewmat_dev.copy_(bs.viewmat_host, non_blocking=True)
-            if self.use_graphs and bs.uses > 0:
-                if bs.graph is None:
-                    # A set is captured on its second use (a set evicted after
-                    # one request never pays for a capture).  The capture runs
-                    # on the launch stream itself: unlike the torch.cuda.graph
-                    # context it does not synchronise the device, so requests
-                    # on the other streams keep running.
+    def _launch(self, arena: _Arena, batch: list):
+        dev = self.device
+        cams = [self._cam(r.res, r.viewmat) for r in batch]
+        gs = [self.scenes[r.scene] for r in batch]
+        gb, rb, g0, r0 = [], [], 0, 0
+        for g, c in zip(gs, cams):
+            gb.append(g0)
+            rb.append(r0)
+            g0 += g.n
+            r0 += grid_dims(c)[2]
+        key = arena.bucket(g0, r0)
+        layout = BatchLayout(TILES_X, key[1], key[0], gb, rb)
+        t_launch = time.perf_counter()
+        with torch.cuda.stream(arena.stream):
+            arena.stream.wait_event(arena.ready)
+            outs = []
+            for c in cams:
+                hs, ws, _, _ = grid_dims(c)
+                outs.append((torch.empty((4 + self.c_sem, hs, ws), device=dev), torch.empty((hs, ws), device=dev),
+                             torch.empty((hs, ws), dtype=torch.int32, device=dev)))
+            table = batch_table([(g, c, *o) for g, c, o in zip(gs, cams, outs)], layout)
+            xgs_batch_check(table, len(batch), layout, self.c_sem)
+            full = (XgsBatchSlot * self.max_slots)()
+            ctypes.memmove(full, table, ctypes.sizeof(XgsBatchSlot) * len(batch))
+            for k in range(len(batch), self.max_slots):   # unused slots: no Gaussians, no tile rows
+                full[k].cam.stride = 1
+                full[k].gauss_base = layout.cap_gaussians
+                full[k].row_base = layout.tile_rows
+            ctypes.memmove(arena.h_table.data_ptr(), full, ctypes.sizeof(full))
+            arena.d_table.copy_(arena.h_table, non_blocking=True)
+            if self.use_graphs and arena.uses[key] > 0:
+                if key not in arena.graphs:
+                    # captured on the arena's stream on the bucket's second
+                    # batch; the capture does not synchronise the device, so
+                    # the other arena keeps running
                     graph = torch.cuda.CUDAGraph()
                     graph.capture_begin(capture_error_mode="thread_local")
                     try:
-                        bs.enqueue(g)
+                        arena.body(key)
                     finally:
                         graph.capture_end()
-                    bs.graph = graph
+                    arena.graphs[key] = graph
                     self.graphs_captured += 1
-                bs.graph.replay()
+                arena.graphs[key].replay()
             else:
-                bs.enqueue(g)
-            bs.uses += 1
-            image = bs.out.clone()
-            final_T = bs.final_T.clone()
-            bs.status_host.copy_(bs.binning.status, non_blocking=True)
+                arena.body(key)
+            arena.status_host.copy_(arena.binning.status, non_blocking=True)
             ev = torch.cuda.Event()
-            ev.record(s)
-        self._inflight.append((req, bs, ev, image, final_T, time.perf_counter()))
+            ev.record(arena.stream)
+        arena.uses[key] += 1
+        arena.batches += 1
+        self.batches += 1
+        self.batched_requests += len(batch)
+        ob = sum(self._out_nbytes(r.res) for r in batch)
+        self._out_bytes += ob
+        self.peak_ledger_bytes = max(self.peak_ledger_bytes, self.ledger_bytes + self._out_bytes)
+        arena.busy = (batch, layout, outs, ev, t_launch, ob)
 
-    def _finish(self, item):
-        req, bs, ev, image, final_T, t_launch = item
-        if int(bs.status_host.item()) != 0:
-            # Capacity overflow.  The set still holds this request's
-            # projection: count the instances it needed (a small reduction on
-            # a side stream), grow the pair's capacity, drop the undersized
-            # set and put the request back at the head of the queue, so the
-            # loop never blocks on a re-render.
-            with torch.cuda.stream(self._side):
-                self._side.wait_event(ev)
-                m = int(bs.proj.tiles_touched.to(torch.int64).sum().item())
-            self._capacity[bs.key] = max(self._capacity.get(bs.key, 0), int(m * 1.25) + 1024)
+    def _finish(self, arena: _Arena):
+        batch, layout, outs, ev, t_launch, ob = arena.busy
+        arena.busy = None
+        self._out_bytes -= ob
+        if int(arena.status_host.item()) != 0:
+            # Instance overflow: measure each slot's instances from the
+            # projection the arena still holds, raise the estimates, grow the
+            # arena if one request alone needs more, and requeue the batch.
             self.overflows += 1
-            self.ledger_bytes -= bs.nbytes
-            self._pending.appendleft(req)
+            need = [int(arena.proj.tiles_touched[gb:gb + self.scenes[r.scene].n].to(torch.int64).sum().item())
+                    for r, gb in zip(batch, layout.gauss_base)]
+            for r, m in zip(batch, need):
+                self._est[(r.scene, r.res)] = max(self._estimate(r), int(1.25 * m) + 1024)
+            if max(need) > arena.max_instances:
+                self._grow(int(1.25 * max(need)) + 1024)
+            self._pending.extendleft(reversed(batch))
             return
         t = time.perf_counter()
-        res = RenderResult(image, final_T, t - req.t_arrival, t_launch - req.t_arrival)
-        self.completed.append(res)
-        self._release(bs)
-        req.future.set_result(res)
+        for r, (img, fT, _) in zip(batch, outs):
+            res = RenderResult(img, fT, t - r.t_arrival, t_launch - r.t_arrival)
+            self.completed.append((res.latency_s, res.queued_s))
+            r.future.set_result(res)
+
+    def _grow(self, instances: int):
+        """Raises the arenas' instance capacity; idle arenas below it are
+        rebuilt before their next batch (_refresh)."""
+        cap, rows, inst = self._arena_args
+        self._arena_args = (cap, rows, max(instances, inst))
+
+    def _refresh(self, i: int):
+        arena = self.arenas[i]
+        if arena.busy is not None or arena.max_instances >= self._arena_args[2]:
+            return
+        torch.cuda.current_stream().wait_stream(arena.stream)
+        self.ledger_bytes -= arena.nbytes
+        self.arenas[i] = None
+        del arena
+        new = _Arena(self, *self._arena_args)
+        self._charge(new.nbytes)
+        self.arenas[i] = new
+        self.arena_growths += 1
 
     def _loop(self):
-        while not (self._stop.is_set() and self._queue.empty() and not self._pending and not self._inflight):
+        self._ensure_arenas()
+        while not (self._stop.is_set() and self._queue.empty() and not self._pending
+                   and not any(a.busy for a in self.arenas)):
             try:
                 while True:
                     self._pending.append(self._queue.get_nowait())
             except queue.Empty:
                 pass
-            # admit in arrival order while slots and memory allow
-            while self._pending and len(self._inflight) < self.max_inflight:
-                req = self._pending[0]
-                bs = self._acquire(req.scene, req.res, req.viewmat)
-                if bs is None:
-                    if not self._inflight:  # cannot fit even on an idle GPU
-                        self._pending.popleft()
-                        self.rejected += 1
-                        req.future.set_exception(MemoryError("request scratch exceeds the HBM budget"))
-                        continue
-                    break
-                self._pending.popleft()
-                try:
-                    self._launch(req, bs)
-                except Exception as e:  # surface launch errors on the request
-                    self._release(bs)
-                    req.future.set_exception(e)
-            # retire finished work
-            still = []
-            for item in self._inflight:
-                if item[2].query():
-                    self._finish(item)
-                else:
-                    still.append(item)
-            self._inflight = still
-            if not self._pending and not self._inflight:
+            # retire finished batches, then fill every free arena
+            for a in list(self.arenas):
+                if a.busy is not None and a.busy[3].query():
+                    self._finish(a)
+            for i in range(len(self.arenas)):
+                if self.arenas[i].busy is None and self._pending:
+                    self._refresh(i)
+                    a = self.arenas[i]
+                    batch = self._form_batch(a)
+                    if batch:
+                        try:
+                            self._launch(a, batch)
+                        except Exception as e:  # surface launch errors on the requests
+                            for r in batch:
+                                r.future.set_exception(e)
+            if not self._pending and not any(a.busy for a in self.arenas):
                 try:
                     self._pending.append(self._queue.get(timeout=0.001))
                 except queue.Empty:

@@ -1,6 +1,7 @@
 """Serving form: continuous batching over resident scenes.  Each request's
-image is bit-identical alone and in a mix; graph replays equal eager runs;
-admission respects the HBM budget; capacity overflow is recovered."""
+image is bit-identical alone, in a batched mix and through the single-request
+calls; graph replays equal eager runs; batches form under load; admission
+respects the HBM budget; capacity overflow is recovered."""
 import numpy as np
 import pytest
 import torch
@@ -78,36 +79,46 @@ def test_graph_replays_match_eager(xgs, world):
 
 
 def test_admission_respects_budget(xgs, world):
+    """The arenas and the outputs in flight stay within the budget; a
+    request that cannot fit an arena under a tiny budget fails."""
     from paper_2603_09632_amd.serve import Server
     scenes, res, reqs = world
-    srv = Server(scenes, hbm_budget_bytes=1 << 30, max_inflight=8)
-    one = srv._estimate("room2", res[2])
-    srv.close()
-    budget = int(2.5 * one)
+    budget = 512 << 20
     srv = Server(scenes, hbm_budget_bytes=budget, max_inflight=8)
     futs = [srv.submit("room2", synth.room_trajectory(100, seed=10)[k], res[2]) for k in range(10)]
     for f in futs:
         f.result(timeout=120)
     assert srv.peak_ledger_bytes <= budget
     srv.close()
-    tiny = Server(scenes, hbm_budget_bytes=one // 4, max_inflight=8)
+    tiny = Server(scenes, hbm_budget_bytes=8 << 20, max_inflight=8)
     with pytest.raises(MemoryError):
         tiny.submit("room2", synth.room_trajectory(100, seed=10)[0], res[2]).result(timeout=60)
     tiny.close()
 
 
+def test_batches_form_under_load(xgs, world):
+    """Requests submitted together are rendered in multi-request batches."""
+    from paper_2603_09632_amd.serve import Server
+    scenes, res, reqs = world
+    srv = Server(scenes, max_inflight=8, streams=1)
+    futs = [srv.submit(sc, vm, r) for sc, vm, r in reqs]
+    for f in futs:
+        f.result(timeout=120)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["batches"] < len(reqs) and st["mean_batch"] > 1.5
+
+
 def test_capacity_overflow_is_recovered(xgs, world):
     from paper_2603_09632_amd.serve import Server
     scenes, res, reqs = world
-    srv = Server(scenes, max_inflight=2)
+    srv = Server(scenes, max_inflight=2, max_instances=1000)   # far too small: the first batch overflows
     sc, vm, r = "room1", synth.room_trajectory(100, seed=10)[3], res[1]
-    srv._capacity[(sc, r)] = 1000  # far too small: the graph's sort overflows
     img = np_(srv.render_now(sc, vm, r).image)
-    assert srv.overflows == 1
-    # the undersized set was dropped: the next request gets a set that fits
+    assert srv.overflows == 1 and srv.arena_growths >= 1
+    # the grown arena holds the next request of the pair
     img2 = np_(srv.render_now(sc, vm, r).image)
     assert srv.overflows == 1
-    assert srv.ledger_bytes > 0
     srv.close()
     ref = np_(direct(xgs, scenes[sc], vm, r))
     np.testing.assert_array_equal(img, ref)
