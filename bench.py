@@ -509,8 +509,10 @@ def serving(xgs, synth, dev, n_requests):
     """Serving form: 8 resident rooms of 100k..1M Gaussians (16 semantic
     channels), requests for a random scene, trajectory pose and resolution in
     {320x240, 640x480, 1200x680}, rendered in batches (continuous batching
-    over two arenas).  Saturation throughput is measured with all requests
-    queued at once; then Poisson arrivals at 50% and 80% of it give p50/p99."""
+    over four arenas).  Saturation throughput is measured with all requests
+    queued at once (full batches) and as the highest Poisson rate the server
+    sustains; Poisson arrivals at 50% and 80% of the sustained rate give
+    p50/p99."""
     import torch
 
     from paper_2603_09632_amd.serve import Resolution, Server, poisson_load
@@ -528,25 +530,48 @@ def serving(xgs, synth, dev, n_requests):
     rng = np.random.default_rng(48)
     mk = lambda m: [(f"room{rng.integers(0, 8)}", poses[rng.integers(0, 100)], res[rng.integers(0, 3)])
                     for _ in range(m)]
-    srv = Server(scenes, hbm_budget_bytes=4 << 30, max_inflight=8, streams=2)
-    for f in [srv.submit(*r) for r in mk(200)]:  # warm-up: buffer sets and graphs
+    srv = Server(scenes, hbm_budget_bytes=4 << 30, max_inflight=8, streams=4)
+    for f in [srv.submit(*r, discard=True) for r in mk(200)]:  # warm-up
         f.result()
     srv.completed.clear()
     burst = mk(n_requests)
     b0 = (srv.batches, srv.batched_requests)
     t0 = time.perf_counter()
-    for f in [srv.submit(*r) for r in burst]:
+    for f in [srv.submit(*r, discard=True) for r in burst]:
         f.result()
     sat = n_requests / (time.perf_counter() - t0)
     sat_batch = (srv.batched_requests - b0[1]) / max(srv.batches - b0[0], 1)
     srv.completed.clear()
+
+    def poisson_run(qps, n, seed):
+        t0 = time.perf_counter()
+        futs = poisson_load(srv, mk(n), qps, seed=seed, discard=True)
+        for f in futs:
+            f.result()
+        return n / (time.perf_counter() - t0)
+
+    # Sustained saturation: the highest Poisson arrival rate the server keeps
+    # up with (achieved >= 97% of offered), by bisection between 30% and 100%
+    # of the burst rate (1,000 requests per probe).  Burst batches are full,
+    # Poisson batches smaller, so the sustained rate is the lower one.
+    lo, hi = 0.3 * sat, sat
+    for it in range(5):
+        mid = 0.5 * (lo + hi)
+        got = poisson_run(mid, 1000, 60 + it)
+        srv.completed.clear()
+        if got >= 0.97 * mid:
+            lo = mid
+        else:
+            hi = mid
+    sustained = lo
+    log(f"serving: burst {sat:.0f} frames/s, sustained Poisson {sustained:.0f} req/s")
     points = []
     for frac, seed in ((0.5, 49), (0.8, 50)):
-        qps = frac * sat
-        log(f"serving: saturation {sat:.0f} frames/s, Poisson run at {frac:.0%} = {qps:.0f} req/s")
+        qps = frac * sustained
+        log(f"serving: Poisson run at {frac:.0%} of the sustained rate = {qps:.0f} req/s")
         c0 = (srv.batches, srv.batched_requests, srv.graphs_captured, srv.overflows)
         t0 = time.perf_counter()
-        futs = poisson_load(srv, mk(n_requests), qps, seed=seed)
+        futs = poisson_load(srv, mk(n_requests), qps, seed=seed, discard=True)
         for f in futs:
             f.result()
         wall = time.perf_counter() - t0
@@ -568,9 +593,11 @@ def serving(xgs, synth, dev, n_requests):
     return {"scenes": "8 rooms, 100k-1M Gaussians, 16 semantic channels",
             "resolutions": "320x240 / 640x480 / 1200x680 uniform", "requests": n_requests, "warmup_requests": 200,
             "saturation_frames_per_s": round(sat, 1), "saturation_mean_batch": round(sat_batch, 2),
+            "sustained_poisson_req_per_s": round(sustained, 1),
+            "load_reference": "load points are fractions of the sustained Poisson rate",
             "load_points": points, "p99_ms_at_80pct": points[-1]["p99_ms"], "peak_hbm_MB": round(peak, 1),
             "hbm_budget_MB": 4096, "capacity_overflows": overflows, "arena_growths": growths, "max_slots": 8,
-            "arenas": 2, "hip_graphs": True,
+            "arenas": 4, "hip_graphs": True,
             "batching": "one project + tile sort + compositing launch sequence per batch, keyed by (slot, tile, "
                         "depth); one HIP graph per arena and capacity bucket"}
 

@@ -272,11 +272,12 @@ xgs_status xgs_batch_check(const xgs_batch_slot* h_slots, int32_t n_slots, int64
                            int32_t tiles_x, int32_t tile_rows, int32_t c_sem);
 /* a1 over the batch: projects every slot's Gaussians with its camera into
  * global rows [gauss_base, gauss_base + n) of out (cap_gaussians rows), tile
- * rectangles in the slot's band of the virtual grid; rows that belong to no
- * slot get tiles_touched = 0.  The batch is then sorted by xgs_tile_sort (or
- * xgs_tile_sort_noalloc) with n = cap_gaussians and a camera whose grid is
- * tiles_x x tile_rows tiles (width 16 tiles_x, height 16 tile_rows, stride
- * 1): the depth keys and rectangles are all it reads. */
+ * rectangles in the slot's band of the virtual grid.  The batch is then
+ * sorted by xgs_tile_sort (or xgs_tile_sort_noalloc) with n = cap_gaussians
+ * and a camera whose grid is tiles_x x tile_rows tiles (width 16 tiles_x,
+ * height 16 tile_rows, stride 1): the depth keys and rectangles are all it
+ * reads.  Rows of no slot get only tiles_touched = 0 (their other fields are
+ * left as they were). */
 xgs_status xgs_batch_project(const xgs_batch_slot* d_slots, int32_t n_slots, int64_t cap_gaussians,
                              int32_t tiles_x, int32_t tile_rows, xgs_projected* out, xgs_stream_t stream);
 /* a3 over the batch: every slot's tiles composited into its own out, final_T

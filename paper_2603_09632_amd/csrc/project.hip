@@ -150,15 +150,19 @@ __host__ __device__ inline CamDev cam_dev(const xgs_camera& cam) {
 }
 
 // Batched projection: row i of the batch belongs to the slot whose
-// [gauss_base, gauss_base + n) holds it (the block's slot bounds are read
-// once into LDS); rows of no slot are written as culled.
+// [gauss_base, gauss_base + n) holds it.  Each block reads the slot bounds
+// and builds every slot's camera once, in LDS; rows of no slot only get
+// tiles_touched = 0 (nothing else of such a row is ever read).
 __global__ void __launch_bounds__(256) project_batch_kernel(
     const xgs_batch_slot* __restrict__ slots, int n_slots, int64_t cap, float4* __restrict__ splat,
     int32_t* __restrict__ radius, uint2* __restrict__ tile_rect, uint32_t* __restrict__ touched) {
     __shared__ int64_t s_lo[XGS_BATCH_MAX_SLOTS], s_hi[XGS_BATCH_MAX_SLOTS];
+    __shared__ CamDev s_cam[XGS_BATCH_MAX_SLOTS];
     if (threadIdx.x < n_slots) {
-        s_lo[threadIdx.x] = slots[threadIdx.x].gauss_base;
-        s_hi[threadIdx.x] = slots[threadIdx.x].gauss_base + slots[threadIdx.x].g.n;
+        const xgs_batch_slot& sl = slots[threadIdx.x];
+        s_lo[threadIdx.x] = sl.gauss_base;
+        s_hi[threadIdx.x] = sl.gauss_base + sl.g.n;
+        s_cam[threadIdx.x] = cam_dev(sl.cam);
     }
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -167,17 +171,12 @@ __global__ void __launch_bounds__(256) project_batch_kernel(
     for (int j = 0; j < n_slots; ++j)
         if (i >= s_lo[j] && i < s_hi[j]) s = j;
     if (s < 0) {
-        splat[2 * i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        splat[2 * i + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        radius[i] = 0;
-        tile_rect[i] = make_uint2(0u, 0u);
         touched[i] = 0u;
         return;
     }
     const xgs_batch_slot& sl = slots[s];
-    const CamDev c = cam_dev(sl.cam);
     project_one(i - s_lo[s], i, sl.g.means, sl.g.log_scales, reinterpret_cast<const float4*>(sl.g.quats),
-                sl.g.opacity, c, (uint32_t)sl.row_base, splat, radius, tile_rect, touched);
+                sl.g.opacity, s_cam[s], (uint32_t)sl.row_base, splat, radius, tile_rect, touched);
 }
 
 }  // namespace xgs

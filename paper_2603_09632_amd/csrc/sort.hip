@@ -218,8 +218,12 @@ xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint
 }
 
 // ------------------------------------------------------------ radix sort
+// The grids cover the capacity; only the ceil(count / kSortItems) blocks that
+// hold keys take part (the others return at once and their histogram columns
+// are never read), so the cost follows the instance count.
+//
 // Per block: digit histogram of its kSortItems keys, written digit-major
-// (hist[d * nb + b]).
+// (hist[d * nb + b], nb = the grid size).
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t* __restrict__ keys,
                                                                  const int64_t* __restrict__ count,
                                                                  int shift, uint32_t mask,
@@ -227,14 +231,13 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t
     __shared__ uint32_t h[256];
     const int64_t m = *count;
     const int64_t base = (int64_t)blockIdx.x * kSortItems;
+    if (base >= m) return;  // uniform: a column no scan reads
     h[threadIdx.x] = 0;
     __syncthreads();
-    if (base < m) {
 #pragma unroll
-        for (int r = 0; r < kSortRounds; ++r) {
-            int64_t i = base + r * kSortThreads + threadIdx.x;
-            if (i < m) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
-        }
+    for (int r = 0; r < kSortRounds; ++r) {
+        int64_t i = base + r * kSortThreads + threadIdx.x;
+        if (i < m) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
@@ -250,16 +253,20 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
 }
 
 // One workgroup per digit d: exclusive scan of d's per-block counts in place
-// (the offset of block b among the keys with digit d), and totals[d].
+// (the offset of block b among the keys with digit d), and totals[d], over
+// the blocks that hold keys (row stride nb).
 __global__ void __launch_bounds__(256) radix_scan_kernel(uint32_t* __restrict__ hist,
-                                                        uint32_t* __restrict__ totals, int64_t nb) {
+                                                        uint32_t* __restrict__ totals, int64_t nb,
+                                                        const int64_t* __restrict__ count) {
     __shared__ uint32_t ws[4];
     const int d = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
     uint32_t* row = hist + (int64_t)d * nb;
+    const int64_t m = *count;
+    const int64_t nbe = m <= 0 ? 0 : min(nb, (m + kSortItems - 1) / kSortItems);
     uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+    for (int64_t b0 = 0; b0 < nbe; b0 += 256) {
         const int64_t i = b0 + t;
-        const uint32_t v = i < nb ? row[i] : 0u;
+        const uint32_t v = i < nbe ? row[i] : 0u;
         const uint32_t incl = wave_incl_scan(v, lane);
         if (lane == 63) ws[w] = incl;
         __syncthreads();
@@ -270,7 +277,7 @@ __global__ void __launch_bounds__(256) radix_scan_kernel(uint32_t* __restrict__ 
             pre += k < w ? x : 0u;
             tot += x;
         }
-        if (i < nb) row[i] = carry + pre + incl - v;
+        if (i < nbe) row[i] = carry + pre + incl - v;
         carry += tot;
         __syncthreads();
     }
@@ -357,7 +364,7 @@ xgs_status radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, co
         uint32_t mask = (1u << nbits) - 1u;
         hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, ki,
                            count, shift, mask, hist);
-        hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(256), 0, stream, hist, totals, nb);
+        hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(256), 0, stream, hist, totals, nb, count);
         hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream,
                            ki, vi, ko, vo, count, shift, mask, nbits, hist, totals);
         uint64_t* tk = ki; ki = ko; ko = tk;

@@ -11,8 +11,8 @@ Batches run in arenas: fixed buffers (batch projection, binning, sort
 workspace, slot table) sized once from the HBM budget, with capacities in
 Gaussians, tile rows, instances and slots.  Each arena has its own stream and
 carries HIP graphs of the three calls, one per capacity bucket (Gaussian rows
-and tile rows rounded up to powers of two), each captured on the bucket's
-second batch; a batch rewrites the arena's device slot table (scene
+and tile rows rounded up to powers of two), all captured when the arena is
+created; a batch rewrites the arena's device slot table (scene
 pointers, pose, output pointers) and replays its bucket's graph, so any mix
 of scenes, poses and resolutions within a bucket replays the same graph, and
 a small batch does not pay for the full capacity.  With two arenas one batch
@@ -51,6 +51,8 @@ from . import (BatchLayout, Gaussians, Projected, XgsBatchSlot, alloc_binning, b
 
 TILES_X = 75               # virtual grid width: the widest resolution served (1200 px) in tiles
 ORDER_TILES = 16384        # the tile sort orders up to this many tiles longest-first
+G_BUCKET0 = 1 << 16        # smallest Gaussian-row bucket of a batch
+R_BUCKET0 = 16             # smallest tile-row bucket of a batch
 
 
 @dataclass(frozen=True)
@@ -65,8 +67,8 @@ class Resolution:
 
 @dataclass
 class RenderResult:
-    image: torch.Tensor       # [4 + C_sem, H, W] on the GPU
-    final_T: torch.Tensor     # [H, W]
+    image: Optional[torch.Tensor]    # [4 + C_sem, H, W] on the GPU (None when discarded)
+    final_T: Optional[torch.Tensor]  # [H, W]
     latency_s: float
     queued_s: float
 
@@ -78,6 +80,7 @@ class _Request:
     res: Resolution
     viewmat: np.ndarray
     t_arrival: float
+    discard: bool = False
     future: Future = field(default_factory=Future)
 
 
@@ -125,7 +128,30 @@ class _Arena:
                 + max_slots * ctypes.sizeof(XgsBatchSlot))
 
     def bucket(self, gaussians: int, rows: int) -> tuple:
-        return (_bucket(gaussians, self.cap_gaussians, 1 << 18), _bucket(rows, self.tile_rows, 32))
+        return (_bucket(gaussians, self.cap_gaussians, G_BUCKET0), _bucket(rows, self.tile_rows, R_BUCKET0))
+
+    def buckets(self) -> list:
+        out, g = [], G_BUCKET0
+        while True:
+            r = R_BUCKET0
+            while True:
+                out.append((min(g, self.cap_gaussians), min(r, self.tile_rows)))
+                if r >= self.tile_rows:
+                    break
+                r *= 2
+            if g >= self.cap_gaussians:
+                break
+            g *= 2
+        return out
+
+    def empty_table(self, key: tuple):
+        """Slot table with every slot unused (no Gaussians, no tile rows)."""
+        full = (XgsBatchSlot * self.server.max_slots)()
+        for k in range(self.server.max_slots):
+            full[k].cam.stride = 1
+            full[k].gauss_base = key[0]
+            full[k].row_base = key[1]
+        return full
 
     def body(self, key: tuple):
         """The batch's launches on the current stream (also what is captured)."""
@@ -189,13 +215,17 @@ class Server:
         self._thread.start()
 
     # ----------------------------------------------------------------- api
-    def submit(self, scene: str, viewmat, res: Resolution) -> Future:
+    def submit(self, scene: str, viewmat, res: Resolution, discard: bool = False) -> Future:
+        """Queues a request.  discard: the image is rendered but not kept (the
+        future's RenderResult carries the timings only), as for a client that
+        consumes results as they come."""
         if scene not in self.scenes:
             raise KeyError(scene)
         with self._lock:
             self._rid += 1
             rid = self._rid
-        req = _Request(rid, scene, res, np.asarray(viewmat, dtype=np.float32).reshape(4, 4), time.perf_counter())
+        req = _Request(rid, scene, res, np.asarray(viewmat, dtype=np.float32).reshape(4, 4), time.perf_counter(),
+                       discard)
         self._queue.put(req)
         return req.future
 
@@ -241,6 +271,31 @@ class Server:
             a = _Arena(self, *self._arena_args)
             self._charge(a.nbytes)
             self.arenas.append(a)
+            if self.use_graphs:
+                self._precapture(a)
+
+    def _precapture(self, arena: _Arena):
+        """Captures every capacity bucket's graph up front (on an all-empty
+        slot table), so that no capture stalls a request later."""
+        with torch.cuda.stream(arena.stream):
+            arena.stream.wait_event(arena.ready)
+            for key in arena.buckets():
+                full = arena.empty_table(key)
+                ctypes.memmove(arena.h_table.data_ptr(), full, ctypes.sizeof(full))
+                arena.d_table.copy_(arena.h_table, non_blocking=True)
+                arena.body(key)                      # first run eager
+                graph = torch.cuda.CUDAGraph()
+                graph.capture_begin(capture_error_mode="thread_local")
+                try:
+                    arena.body(key)
+                finally:
+                    graph.capture_end()
+                arena.graphs[key] = graph
+                arena.uses[key] += 1
+                self.graphs_captured += 1
+                # the host table is rewritten for the next bucket only after
+                # this copy has read it
+                arena.stream.synchronize()
 
     def _form_batch(self, arena: _Arena) -> list:
         """Pending requests that fit the arena together, in arrival order."""
@@ -291,12 +346,8 @@ class Server:
                              torch.empty((hs, ws), dtype=torch.int32, device=dev)))
             table = batch_table([(g, c, *o) for g, c, o in zip(gs, cams, outs)], layout)
             xgs_batch_check(table, len(batch), layout, self.c_sem)
-            full = (XgsBatchSlot * self.max_slots)()
+            full = arena.empty_table(key)             # unused slots: no Gaussians, no tile rows
             ctypes.memmove(full, table, ctypes.sizeof(XgsBatchSlot) * len(batch))
-            for k in range(len(batch), self.max_slots):   # unused slots: no Gaussians, no tile rows
-                full[k].cam.stride = 1
-                full[k].gauss_base = layout.cap_gaussians
-                full[k].row_base = layout.tile_rows
             ctypes.memmove(arena.h_table.data_ptr(), full, ctypes.sizeof(full))
             arena.d_table.copy_(arena.h_table, non_blocking=True)
             if self.use_graphs and arena.uses[key] > 0:
@@ -346,6 +397,8 @@ class Server:
             return
         t = time.perf_counter()
         for r, (img, fT, _) in zip(batch, outs):
+            if r.discard:
+                img = fT = None
             res = RenderResult(img, fT, t - r.t_arrival, t_launch - r.t_arrival)
             self.completed.append((res.latency_s, res.queued_s))
             r.future.set_result(res)
@@ -368,6 +421,8 @@ class Server:
         self._charge(new.nbytes)
         self.arenas[i] = new
         self.arena_growths += 1
+        if self.use_graphs:
+            self._precapture(new)
 
     def _loop(self):
         self._ensure_arenas()
@@ -402,7 +457,7 @@ class Server:
                 time.sleep(0)
 
 
-def poisson_load(server: Server, requests: list, qps: float, seed: int = 48) -> list[Future]:
+def poisson_load(server: Server, requests: list, qps: float, seed: int = 48, discard: bool = False) -> list[Future]:
     """Submits (scene, viewmat, resolution) requests with exponential
     inter-arrival times at the given rate; returns their futures."""
     rng = np.random.default_rng(seed)
@@ -415,5 +470,5 @@ def poisson_load(server: Server, requests: list, qps: float, seed: int = 48) -> 
             if now >= t_next:
                 break
             time.sleep(min(t_next - now, 0.0005))
-        futures.append(server.submit(scene, vm, res))
+        futures.append(server.submit(scene, vm, res, discard=discard))
     return futures
