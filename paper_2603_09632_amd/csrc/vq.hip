@@ -1,18 +1,32 @@
 // a6/a7: nearest-codeword assignment and the EMA codebook update of the
 // online VQ module (Sec. 3.2.2, Eq. (ema_update)).
 //
-// Assignment, BF16 form: the distance contraction is the only dense GEMM on
-// the hot path, so it runs on MFMA.  A workgroup keeps 64 rows of X resident
-// in LDS as bf16 and its four wavefronts sweep the codebook (bf16 shadow read
-// straight from L2 into registers), each computing a 64-row x 128-codeword
-// tile per step with v_mfma_f32_32x32x16_bf16.  The accumulators start at
-// -||e^||^2/2, so each output is x^.e^ - ||e^||^2/2 and the nearest codeword
-// is the largest.  Every lane keeps a running top-4 per row; the candidates
-// are merged through LDS and rescored with the direct FP32 form sum (x - e)^2.
+// Assignment, BF16 form (precision form): the distance contraction is the
+// only dense GEMM on the hot path, so it runs on MFMA in three stages.
+//  1. Staging: X and the codebook are rounded to bf16 and written
+//     chunk-tiled (for a block of rows, the 32 columns of a chunk are
+//     contiguous row after row) with one extra chunk per row that carries the
+//     squared norm as three bf16 pieces against ones on the other operand,
+//     so the plain dot product of two staged rows is half their squared
+//     distance (the ranking key); padded codewords carry +inf.
+//  2. Sweep: a workgroup owns 128 X rows and one codebook part (at least 4
+//     parts; the parts of a row block go to one XCD so its X chunks are read
+//     once into one L2), swept in 256-codeword tiles.  Both operands arrive by
+//     direct global->LDS loads (three chunk buffers, two chunks ahead); four
+//     wavefronts each accumulate 64 rows x 128 codewords with
+//     v_mfma_f32_32x32x16_bf16 in FP32, and each lane keeps a running top-4
+//     per row of 32-bit rank keys (distance with the candidate's position in
+//     its low bits, so ties go to the lower index).  The optional confidence
+//     epilogue keeps an online log-sum-exp per row and part.
+//  3. Rescore: the 4 x parts candidates of a row are reduced to the best 4
+//     and rescored with the direct FP32 form sum (x - e)^2; the smallest wins
+//     (lowest index on ties).
+// The FP32 plain path (vq_fp32_kernel) tiles the direct form through LDS.
 //
 // Update: rows are grouped by codeword with the stable radix sort, each
-// codeword's rows are summed in ascending row order (bitwise reproducible),
-// and one pass applies the EMA and refreshes the bf16 shadow and its norms.
+// codeword's rows are summed as pieces of at most 128 rows whose sums are
+// added in piece order (bitwise reproducible), and one pass applies the EMA
+// and refreshes the bf16 shadow and its norms.
 #include <algorithm>
 
 #include "sort.h"
