@@ -59,6 +59,12 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
     bool my_own = false;
     if (GEO) rs_layout<2 * VG>(lane, &my_id, &my_own);
     const int my_split = my_id / VG, my_v = my_id - VG * (my_id / VG);  // splat of the pair, sum
+    // the array and stride that this lane's sum goes to (lane-constant, so the
+    // walk adds without branching on the destination)
+    float* const g_base = my_v == 0 ? d_opacity
+                                    : geo + (my_v == 1 ? GW_A : my_v == 2 ? GW_B : my_v == 3 ? GW_C
+                                                        : my_v == 4 ? GW_MX : GW_MY);
+    const int g_stride = my_v == 0 ? 1 : GW_STRIDE;
     const size_t hw = (size_t)g.hs * g.ws;
     const int fstride = EXACT ? CS : csem;
     const int qx = P.n - (lane & 7), qy = P.m - (lane >> 3);  // quadrant origin
@@ -182,55 +188,42 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
             int gp[2] = {-1, -1};
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
+                // branch-free: slots past the batch are read (in bounds) and
+                // every result is selected, so stale records change nothing
                 const int k = k2 + u;
-                float w = 0.f;
-                if (k < nb) {
-                    const int at = (head + k) & (kRing - 1);
-                    const float4 s0 = ring.rec[at][0];
-                    const float4 s1 = ring.rec[at][1];
-                    gp[u] = ring.gid[at];
-                    const int j = ring.pos[at];
-                    const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
-                    const bool contrib = j < nl && e.alpha >= kAlphaMin;
-                    if (contrib) {
-                        const float om = 1.f - e.alpha;  // >= 0.01
-                        const float rom = __builtin_amdgcn_rcpf(om);
-                        const float Tk = T * rom;
-                        w = e.alpha * Tk;
-                        if (GEO) {
-                            const float sd = sdl[lane * 17 + k];
-                            const float dalpha = Tk * sd - S * rom;
-                            const bool clamped = !(s1.y * e.G < kAlphaMax);
-                            const float dq = clamped ? 0.f : dalpha * s1.y * e.G * -0.5f;
-                            a[VG * u + 0] = clamped ? 0.f : dalpha * e.G;
-                            a[VG * u + 1] = dq * e.dx * e.dx;
-                            a[VG * u + 2] = 2.f * dq * e.dx * e.dy;
-                            a[VG * u + 3] = dq * e.dy * e.dy;
-                            a[VG * u + 4] = -2.f * dq * (s0.z * e.dx + s0.w * e.dy);
-                            a[VG * u + 5] = -2.f * dq * (s0.w * e.dx + s1.x * e.dy);
-                            S += w * sd;
-                        }
-                        T = Tk;
-                        any = true;
-                    }
+                const int at = (head + k) & (kRing - 1);
+                const float4 s0 = ring.rec[at][0];
+                const float4 s1 = ring.rec[at][1];
+                gp[u] = k < nb ? ring.gid[at] : -1;
+                const int j = ring.pos[at];
+                const PairEval e = eval_pair(P.px, P.py, s0.x, s0.y, s0.z, s0.w, s1.x, s1.y);
+                const bool contrib = k < nb && j < nl && e.alpha >= kAlphaMin;
+                const float om = 1.f - e.alpha;  // >= 0.01
+                const float rom = __builtin_amdgcn_rcpf(om);
+                const float Tk = T * rom;
+                const float wv = e.alpha * Tk;
+                if (GEO) {
+                    const float sd = sdl[lane * 17 + k];
+                    const float dalpha = Tk * sd - S * rom;
+                    const bool live = contrib && s1.y * e.G < kAlphaMax;
+                    const float dq = dalpha * s1.y * e.G * -0.5f;
+                    a[VG * u + 0] = live ? dalpha * e.G : 0.f;
+                    a[VG * u + 1] = live ? dq * e.dx * e.dx : 0.f;
+                    a[VG * u + 2] = live ? 2.f * dq * e.dx * e.dy : 0.f;
+                    a[VG * u + 3] = live ? dq * e.dy * e.dy : 0.f;
+                    a[VG * u + 4] = live ? -2.f * dq * (s0.z * e.dx + s0.w * e.dy) : 0.f;
+                    a[VG * u + 5] = live ? -2.f * dq * (s0.w * e.dx + s1.x * e.dy) : 0.f;
+                    S = contrib ? S + wv * sd : S;
                 }
+                T = contrib ? Tk : T;
+                const float w = contrib ? wv : 0.f;
+                any = any || contrib;
                 wl[lane * 17 + k] = w;
             }
             if (GEO && k2 < nb && __ballot(any) != 0ull) {
                 reduce_scatter<2 * VG>(a, lane);
                 const int gid = my_split ? gp[1] : gp[0];
-                if (my_own && gid >= 0) {
-                    float* dst;
-                    switch (my_v) {
-                        case 0: dst = d_opacity + gid; break;
-                        case 1: dst = geo + (size_t)gid * GW_STRIDE + GW_A; break;
-                        case 2: dst = geo + (size_t)gid * GW_STRIDE + GW_B; break;
-                        case 3: dst = geo + (size_t)gid * GW_STRIDE + GW_C; break;
-                        case 4: dst = geo + (size_t)gid * GW_STRIDE + GW_MX; break;
-                        default: dst = geo + (size_t)gid * GW_STRIDE + GW_MY; break;
-                    }
-                    unsafeAtomicAdd(dst, a[0]);
-                }
+                if (my_own && gid >= 0) unsafeAtomicAdd(g_base + (size_t)gid * g_stride, a[0]);
             }
         }
         __syncthreads();
@@ -251,15 +244,13 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
             if (gs < 0) continue;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
+                // channel c of this lane: colour, depth (workspace row) or feature
                 const int c = 16 * nt + (lane & 15);
+                const bool ok = c < CH && (EXACT || c < 4 + csem) && (GEO || c >= 4);
+                float* const base = c < 3 ? d_colors + c : c == 3 ? geo + GW_DEPTH : d_features + (c - 4);
+                const int stride = c < 3 ? 3 : c == 3 ? (int)GW_STRIDE : fstride;
                 const float v = acc[nt][r];
-                if (c >= CH || v == 0.f) continue;
-                float* dst;
-                if (c < 3) dst = d_colors + 3 * (size_t)gs + c;
-                else if (c == 3) dst = geo + (size_t)gs * GW_STRIDE + GW_DEPTH;
-                else if (EXACT || c - 4 < csem) dst = d_features + (size_t)gs * fstride + (c - 4);
-                else continue;
-                if (GEO || c >= 4) unsafeAtomicAdd(dst, v);
+                if (ok && v != 0.f) unsafeAtomicAdd(base + (size_t)gs * stride, v);
             }
         }
         __syncthreads();
