@@ -223,8 +223,16 @@ xgs_status xgs_render_fwd(const xgs_gaussians* g, const xgs_projected* p, const 
  * flags: XGS_BWD_FEATURES_ONLY computes only d_features (geometry frozen,
  * Sec. 3.2.2 "decouple"); the other gradient pointers may then be NULL.
  * ws must hold xgs_render_bwd_workspace(n) bytes, 256-byte aligned. */
-enum { XGS_BWD_ALL = 0, XGS_BWD_FEATURES_ONLY = 1 };
+enum { XGS_BWD_ALL = 0, XGS_BWD_FEATURES_ONLY = 1, XGS_BWD_PREZEROED = 2 };
 size_t xgs_render_bwd_workspace(int64_t n);
+/* The zeroing that xgs_render_bwd does first, as a call of its own: the
+ * accumulated gradients (features; with XGS_BWD_ALL also colours and
+ * opacity) and the workspace's per-Gaussian rows.  A caller can issue it
+ * earlier, on another stream (overlapping the forward pass), and then call
+ * xgs_render_bwd with flags | XGS_BWD_PREZEROED on the same grads and ws,
+ * which then skips its own zeroing; the caller orders the two (an event). */
+xgs_status xgs_render_bwd_zero(const xgs_gaussians* g, int32_t flags, xgs_gaussians_grad* grads, void* ws,
+                               size_t ws_bytes, xgs_stream_t stream);
 xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected* p, const xgs_binning* b,
                           const xgs_camera* cam, const float* d_out, const float* final_T,
                           const int32_t* n_last, int32_t flags, xgs_gaussians_grad* grads,

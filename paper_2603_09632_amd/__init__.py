@@ -28,12 +28,12 @@ SPLAT_STRIDE = 8
 GRID_BILINEAR, GRID_NEAREST = 0, 1
 VQ_FP32, VQ_BF16_RESCORE4 = 0, 1
 EMA_PAPER, EMA_LAPLACE = 0, 1
-BWD_ALL, BWD_FEATURES_ONLY = 0, 1
+BWD_ALL, BWD_FEATURES_ONLY, BWD_PREZEROED = 0, 1, 2
 
 __all__ = [
     "XgsError", "Gaussians", "Projected", "Binning", "camera", "camera_from", "grid_dims",
     "xgs_project", "xgs_project_posed", "alloc_binning", "xgs_tile_sort", "xgs_tile_sort_noalloc", "xgs_render_fwd",
-    "xgs_render_bwd",
+    "xgs_render_bwd", "xgs_render_bwd_zero",
     "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_stage", "xgs_vq_candidates", "xgs_vq_rescore",
     "vq_assign_workspace", "xgs_vq_ema_update", "xgs_semantic_softmax", "xgs_semantic_softmax_bwd",
     "xgs_semantic_loss", "semantic_step", "xgs_pose_grad", "xgs_tracking_loss", "tracking_step", "xgs_region_targets",
@@ -338,6 +338,14 @@ def xgs_render_bwd(g: Gaussians, p: Projected, b: Binning, cam, d_out, final_T, 
                              _ptr(final_T), _ptr(n_last), int(flags), ctypes.byref(gr), _ptr(workspace),
                              workspace.numel(), _stream(stream)), "xgs_render_bwd")
     return grads
+
+
+def xgs_render_bwd_zero(g: Gaussians, grads: Gaussians, workspace: torch.Tensor, flags: int = BWD_ALL, stream=None):
+    """The zeroing of xgs_render_bwd on its own (then call it with
+    flags | BWD_PREZEROED)."""
+    gs, gr = g.struct(), grads.struct()
+    check(lib.xgs_render_bwd_zero(ctypes.byref(gs), int(flags), ctypes.byref(gr), _ptr(workspace), workspace.numel(),
+                                  _stream(stream)), "xgs_render_bwd_zero")
 
 
 def xgs_grid_sample(P: torch.Tensor, H: int, W: int, stride: int = 1, off_y: int = 0, off_x: int = 0,

@@ -69,6 +69,7 @@ SIGNATURES = {
                                        P(XgsBinning), c_void_p]),
     "xgs_render_fwd": (c_int32, [P(XgsGaussians), P(XgsProjected), P(XgsBinning), P(XgsCamera),
                                  c_void_p, c_void_p, c_void_p, c_void_p]),
+    "xgs_render_bwd_zero": (c_int32, [P(XgsGaussians), c_int32, P(XgsGaussiansGrad), c_void_p, c_size_t, c_void_p]),
     "xgs_render_bwd_workspace": (c_size_t, [c_int64]),
     "xgs_render_bwd": (c_int32, [P(XgsGaussians), P(XgsProjected), P(XgsBinning), P(XgsCamera),
                                  c_void_p, c_void_p, c_void_p, c_int32, P(XgsGaussiansGrad),

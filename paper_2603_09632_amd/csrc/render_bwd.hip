@@ -525,6 +525,40 @@ extern "C" size_t xgs_render_bwd_workspace(int64_t n) {
     return c.total();
 }
 
+// The accumulated gradients (features; with the geometry also colours,
+// opacity) and the geometry workspace rows start at zero: one launch.
+static xgs_status zero_accumulated(const xgs_gaussians* g, bool geo_on, xgs_gaussians_grad* gr, float* geo,
+                                   hipStream_t st) {
+    ZeroRanges zr{};
+    if (g->c_sem > 0) { zr.p[zr.k] = reinterpret_cast<uint32_t*>(gr->features); zr.n[zr.k++] = g->n * g->c_sem; }
+    if (geo_on) {
+        zr.p[zr.k] = reinterpret_cast<uint32_t*>(gr->colors); zr.n[zr.k++] = 3 * g->n;
+        zr.p[zr.k] = reinterpret_cast<uint32_t*>(gr->opacity); zr.n[zr.k++] = g->n;
+        zr.p[zr.k] = reinterpret_cast<uint32_t*>(geo); zr.n[zr.k++] = GW_STRIDE * g->n;
+    }
+    return zero_ranges(zr, st);
+}
+
+extern "C" xgs_status xgs_render_bwd_zero(const xgs_gaussians* g, int32_t flags, xgs_gaussians_grad* gr, void* ws,
+                                          size_t ws_bytes, xgs_stream_t stream) {
+    clear_error();
+    if (!g || !gr) return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd_zero: null argument");
+    if ((flags & ~XGS_BWD_PREZEROED) != XGS_BWD_ALL && (flags & ~XGS_BWD_PREZEROED) != XGS_BWD_FEATURES_ONLY)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd_zero: unknown flags");
+    const bool geo_on = (flags & ~XGS_BWD_PREZEROED) == XGS_BWD_ALL;
+    if (g->n < 0 || g->c_sem < 0 || g->c_sem > XGS_MAX_C_SEM || gr->n != g->n || gr->c_sem != g->c_sem)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd_zero: gradient shapes differ from the Gaussians");
+    if (!aligned(ws, 256)) return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd_zero: workspace must be 256-byte aligned");
+    if (!ws || ws_bytes < xgs_render_bwd_workspace(g->n))
+        return fail(XGS_ERR_CAPACITY, "xgs_render_bwd_zero: workspace too small");
+    if (g->n == 0) return XGS_OK;
+    if ((g->c_sem > 0 && !gr->features) || (geo_on && (!gr->colors || !gr->opacity)))
+        return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd_zero: null gradient array");
+    xgs_status s = zero_accumulated(g, geo_on, gr, static_cast<float*>(ws), (hipStream_t)stream);
+    if (s) return s;
+    return check_launch("xgs_render_bwd_zero");
+}
+
 extern "C" xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected* p,
                                      const xgs_binning* b, const xgs_camera* cam, const float* d_out,
                                      const float* final_T, const int32_t* n_last, int32_t flags,
@@ -533,6 +567,8 @@ extern "C" xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected
     clear_error();
     if (!g || !p || !b || !cam || !gr) return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: null argument");
     if (xgs_status s = validate_camera(cam)) return s;
+    const bool prezeroed = (flags & XGS_BWD_PREZEROED) != 0;
+    flags &= ~XGS_BWD_PREZEROED;
     if (flags != XGS_BWD_ALL && flags != XGS_BWD_FEATURES_ONLY)
         return fail(XGS_ERR_INVALID_ARG, "xgs_render_bwd: unknown flags");
     const bool geo_on = flags == XGS_BWD_ALL;
@@ -561,15 +597,9 @@ extern "C" xgs_status xgs_render_bwd(const xgs_gaussians* g, const xgs_projected
     hipStream_t st = (hipStream_t)stream;
     float* geo = static_cast<float*>(ws);
     xgs_status s;
-    // the accumulated gradients and the geometry workspace start at zero (one launch)
-    ZeroRanges zr{};
-    if (g->c_sem > 0) { zr.p[zr.k] = reinterpret_cast<uint32_t*>(gr->features); zr.n[zr.k++] = g->n * g->c_sem; }
-    if (geo_on) {
-        zr.p[zr.k] = reinterpret_cast<uint32_t*>(gr->colors); zr.n[zr.k++] = 3 * g->n;
-        zr.p[zr.k] = reinterpret_cast<uint32_t*>(gr->opacity); zr.n[zr.k++] = g->n;
-        zr.p[zr.k] = reinterpret_cast<uint32_t*>(geo); zr.n[zr.k++] = GW_STRIDE * g->n;
-    }
-    if ((s = zero_ranges(zr, st))) return s;
+    // the accumulated gradients and the geometry workspace start at zero (one
+    // launch), unless the caller had xgs_render_bwd_zero do it beforehand
+    if (!prezeroed && (s = zero_accumulated(g, geo_on, gr, geo, st))) return s;
     TileGrid tg = tile_grid(*cam, b->tile_order);
     if (geo_on) {
         dispatch_bwd<true>(g, p, b, tg, d_out, final_T, n_last, gr, geo, st);

@@ -507,3 +507,29 @@ def test_render_bwd_against_central_fd(xgs):
     print(f"FD rel-L2 errors {errs}, counts {counts}")
     assert all(counts[k] >= 0.9 * 64 * (base[k].shape[1] if base[k].ndim == 2 else 1) for k in base), counts
     assert all(v <= 1e-3 for v in errs.values()), errs
+
+
+def test_backward_zeroing_as_a_separate_call(xgs):
+    """xgs_render_bwd_zero on another stream, then xgs_render_bwd with
+    BWD_PREZEROED, gives the gradients of the plain call (the arrays start
+    out full of garbage; only the order of the gradient atomics differs)."""
+    scene = synth.tiny_scene(seed=3)
+    cam = synth.tiny_camera()
+    r = run_render(xgs, scene, cam)
+    hs, ws, _, _ = oracle.grid_info(cam)
+    d_out = torch.from_numpy(synth.upstream_grad(4 + scene.c_sem, hs, ws, seed=5)).cuda()
+    for flags in (xgs.BWD_ALL, xgs.BWD_FEATURES_ONLY):
+        ref = xgs.xgs_render_bwd(r["g"], r["p"], r["b"], r["cam"], d_out, r["final_T"], r["n_last"], flags=flags)
+        grads = xgs.Gaussians(*(torch.full_like(t, 7.0) for t in (r["g"].means, r["g"].log_scales, r["g"].quats,
+                                                                   r["g"].opacity, r["g"].colors, r["g"].features)))
+        ws_ = torch.full((int(xgs.lib.xgs_render_bwd_workspace(scene.n)),), 3, dtype=torch.uint8, device="cuda")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        xgs.xgs_render_bwd_zero(r["g"], grads, ws_, flags=flags, stream=side)
+        torch.cuda.current_stream().wait_stream(side)
+        xgs.xgs_render_bwd(r["g"], r["p"], r["b"], r["cam"], d_out, r["final_T"], r["n_last"],
+                           flags=flags | xgs.BWD_PREZEROED, grads=grads, workspace=ws_)
+        torch.cuda.synchronize()
+        groups = ("features",) if flags == xgs.BWD_FEATURES_ONLY else GROUPS
+        for k in groups:
+            assert rel_max(np_(getattr(grads, k)), np_(getattr(ref, k))) < 1e-5, (flags, k)
