@@ -237,9 +237,9 @@ def main():
     comp = compositing_work(xgs, g, p, b, cams[args.warmup + args.steps - 1], out, fT, nl, scene.c_sem, m_inst,
                             ms["render_fwd"], ms["render_bwd"])
     roofs = [
-        {"kernel": "vq_gemm_kernel", "bound": "mfma", "achieved": round(vq_tflops, 2), "peak": BF16_PEAK_TFLOPS,
+        {"kernel": "vq_gemm_ereg_kernel", "bound": "mfma", "achieved": round(vq_tflops, 2), "peak": BF16_PEAK_TFLOPS,
          "unit": "TFLOP/s", "frac": round(vq_tflops / BF16_PEAK_TFLOPS, 4),
-         "traffic": traffic_for("vq_gemm_kernel", ["vq.hip"], vq_flop),
+         "traffic": traffic_for("vq_gemm_ereg_kernel", ["vq.hip"], vq_flop),
          "algorithmic": f"2*N*K*D = {vq_flop:.3e} flop per launch (N=816000, K=4096, D=768)", "ms": ms["vq_gemm"]},
         comp.pop("roofline_fwd"), comp.pop("roofline_bwd"),
     ]

@@ -11,13 +11,19 @@
 //     distance (the ranking key); padded codewords carry +inf.
 //  2. Sweep: a workgroup owns 128 X rows and one codebook part (at least 4
 //     parts; the parts of a row block go to one XCD so its X chunks are read
-//     once into one L2), swept in 256-codeword tiles.  Both operands arrive by
-//     direct global->LDS loads (three chunk buffers, two chunks ahead); four
-//     wavefronts each accumulate 64 rows x 128 codewords with
-//     v_mfma_f32_32x32x16_bf16 in FP32, and each lane keeps a running top-4
+//     once into one L2), swept in 256-codeword tiles.  Four wavefronts each
+//     accumulate all 128 rows x 64 codewords with v_mfma_f32_32x32x16_bf16 in
+//     FP32: the X chunk goes through LDS (loaded into registers one chunk
+//     ahead, stored into one of two buffers, read by all four), while each
+//     wavefront loads its own codeword fragments straight into registers two
+//     chunks ahead (vq_gemm_ereg_kernel).  Each lane keeps a running top-4
 //     per row of 32-bit rank keys (distance with the candidate's position in
-//     its low bits, so ties go to the lower index).  The optional confidence
-//     epilogue keeps an online log-sum-exp per row and part.
+//     its low bits, so ties go to the lower index).  The confidence form
+//     (an online log-sum-exp per row and part beside the top-4) needs more
+//     registers than that layout leaves, so it runs vq_gemm_kernel, where both
+//     operands arrive by direct global->LDS loads into three chunk buffers and
+//     four wavefronts each accumulate 64 rows x 128 codewords; both sweeps
+//     form the same products in the same order.
 //  3. Rescore: the 4 x parts candidates of a row are reduced to the best 4
 //     and rescored with the direct FP32 form sum (x - e)^2; the smallest wins
 //     (lowest index on ties).
@@ -592,6 +598,277 @@ __global__ void __launch_bounds__(C::THREADS, C::OCC) vq_gemm_kernel(const uint1
     }
 }
 
+// Sweep whose codeword operand bypasses LDS.  WNW wavefronts each own all
+// ROWS = 32 FX rows of the block and 32 FE codewords of every tile.  Each
+// wavefront loads its codeword fragments from global memory straight into
+// registers two chunks ahead; the X chunk is loaded into registers one chunk
+// ahead, written to one of two LDS buffers and read back by every wavefront.
+// Per chunk and workgroup the LDS carries the X chunk once in and WNW times
+// out, instead of both operands in and each operand twice out as in
+// vq_gemm_kernel.  Every load is an ordinary load, so the compiler places
+// all the waits.  Same products in the same order as vq_gemm_kernel, so the
+// accumulators, and the candidates, are bitwise the same.
+template <int FX_, int FE_, int WNW_, int OCC_>
+struct RegCfg {
+    static constexpr int FX = FX_, FE = FE_, WNW = WNW_, OCC = OCC_;
+    static constexpr int NW = WNW, THREADS = 64 * NW;
+    static constexpr int ROWS = FX * 32, COLS = WNW * FE * 32;
+    static constexpr int SLOTS = ROWS * 4;           // 16-byte slots of one X chunk buffer
+    static constexpr int NX = ROWS / (16 * NW);      // X loads per wavefront and chunk
+    static constexpr int NEL = 2 * FE;               // codeword fragment loads per wavefront and chunk
+    static constexpr int LISTS = 2 * WNW;
+    static constexpr int MERGE_U4 = (ROWS * LISTS * 4 * 8 + ROWS * LISTS * 8 + 15) / 16;
+    static constexpr int LDS_U4 = 2 * SLOTS > MERGE_U4 ? 2 * SLOTS : MERGE_U4;
+    static_assert(COLS == Q_BN && FE <= 4 && ROWS % (16 * NW) == 0, "tiling");
+};
+
+// 128 rows x 256 codewords per workgroup, 4 wavefronts of 128 x 64.
+using VqRegCfg = RegCfg<4, 2, 4, 2>;
+static_assert(VqRegCfg::ROWS == VqCfg::ROWS, "both sweeps read X staged in blocks of the same rows");
+
+template <class C, bool CONF>
+__global__ void __launch_bounds__(C::THREADS, C::OCC) vq_gemm_ereg_kernel(const uint16_t* __restrict__ Xa, int64_t N,
+                                                                         int Dx, const uint16_t* __restrict__ Ea, int K,
+                                                                         int parts, int tiles_part, int seq_bits,
+                                                                         int2* __restrict__ cand, float inv_tau,
+                                                                         float2* __restrict__ lse) {
+    constexpr int FX = C::FX, FE = C::FE, NX = C::NX, NEL = C::NEL;
+    constexpr int ROWS = C::ROWS, COLS = C::COLS, NW = C::NW, LISTS = C::LISTS;
+    __shared__ __align__(16) i32x4_t qbuf[C::LDS_U4];
+    const int t = threadIdx.x, lane = t & 63;
+    const int wn = __builtin_amdgcn_readfirstlane(t >> 6);
+    // block -> (row block, part): the parts of one row block share an XCD
+    const int64_t blk = blockIdx.x;
+    const int64_t grp = blk / (8 * parts);
+    const int within = (int)(blk - grp * 8 * parts);
+    const int p = within >> 3;
+    const int64_t rb = grp * 8 + (within & 7);
+    const int64_t r0 = rb * ROWS;
+    if (r0 >= N) return;
+    const int c_part = p * tiles_part * COLS;
+    const int tiles = min(tiles_part, (K - c_part + COLS - 1) / COLS);
+    const int nkc = Dx / Q_BK;
+    const int total = tiles * nkc;
+    const int rows_here = (int)min((int64_t)ROWS, N - r0);
+
+    // X: load m of this lane reads row 16 (wn + NW m) + lane / 4, segment
+    // (lane & 3) ^ q_swz(row), and writes it to slot 64 (wn + NW m) + lane.
+    const int lr = lane >> 2, fr = lane & 31, hf = lane >> 5;
+    const char* xbase = reinterpret_cast<const char*>(Xa + (size_t)rb * nkc * ROWS * Q_BK);
+    uint32_t off[NX];
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+        const int row = 16 * (wn + NW * m) + lr;
+        off[m] = (uint32_t)row * 64u + 16u * (uint32_t)((lane & 3) ^ q_swz(row));
+    }
+    // Codeword fragment (i, ks) of this lane: row wn 32 FE + 32 i + fr of the
+    // tile, segment 2 ks + hf.  Chunk c = tile * nkc + kc of the part is 256
+    // rows x 64 bytes of consecutive memory at c * 16 KB.
+    const char* ebase = reinterpret_cast<const char*>(Ea + (size_t)c_part * Dx) +
+                        (uint32_t)(wn * 32 * FE + fr) * 64u + 16u * (uint32_t)hf;
+    auto load_x = [&](int kc, i32x4_t (&x)[NX]) {
+        const char* xb = xbase + (size_t)kc * (ROWS * Q_BK * 2);
+#pragma unroll
+        for (int m = 0; m < NX; ++m) x[m] = *reinterpret_cast<const i32x4_t*>(xb + off[m]);
+    };
+    auto store_x = [&](int buf, const i32x4_t (&x)[NX]) {
+#pragma unroll
+        for (int m = 0; m < NX; ++m) qbuf[buf * C::SLOTS + 64 * (wn + NW * m) + lane] = x[m];
+    };
+    auto load_e = [&](int c, i32x4_t (&e)[NEL]) {
+        const char* eb = ebase + (size_t)c * (COLS * Q_BK * 2);
+#pragma unroll
+        for (int i = 0; i < FE; ++i)
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+                e[2 * i + ks] = *reinterpret_cast<const i32x4_t*>(eb + 2048 * i + 32 * ks);
+    };
+    int xs0[2], xs1[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        xs0[ks] = q_slot(fr, 2 * ks + hf);
+        xs1[ks] = C::SLOTS + xs0[ks];
+    }
+    auto read_frags = [&](int buf, int ks, i32x4_t (&f)[FX]) {
+        const int s = buf ? xs1[ks] : xs0[ks];
+#pragma unroll
+        for (int jx = 0; jx < FX; ++jx) f[jx] = qbuf[s + 128 * jx];
+    };
+
+    // accumulator r of codeword fragment i holds codeword
+    // tile base + wn 32 FE + 32 i + 8 (r / 4) + 4 hf + r % 4, row 32 jx + fr
+    f32x16_t acc[FE][FX];
+    int top[FX][4];
+#pragma unroll
+    for (int jx = 0; jx < FX; ++jx)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) top[jx][q] = 0x7FFFFFFF;
+    const uint32_t keep = ~((1u << seq_bits) - 1u);
+    float lm[FX], ls[FX];
+#pragma unroll
+    for (int jx = 0; jx < FX; ++jx) { lm[jx] = -INFINITY; ls[jx] = 0.f; }
+    auto tile_lse = [&]() {
+#pragma unroll
+        for (int jx = 0; jx < FX; ++jx) {
+            float mt = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < FE; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    mt = fmaxf(mt, -__builtin_sqrtf(fmaxf(2.f * acc[i][jx][r], 0.f)) * inv_tau);
+            const float mn = fmaxf(lm[jx], mt);
+            if (mn > -INFINITY) {
+                float sum = ls[jx] * __expf(lm[jx] - mn);
+#pragma unroll
+                for (int i = 0; i < FE; ++i)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        sum += __expf(-__builtin_sqrtf(fmaxf(2.f * acc[i][jx][r], 0.f)) * inv_tau - mn);
+                ls[jx] = sum;
+                lm[jx] = mn;
+            }
+        }
+    };
+    auto tile_top4 = [&](int tl) {
+#pragma unroll
+        for (int jx = 0; jx < FX; ++jx)
+#pragma unroll
+            for (int i = 0; i < FE; ++i) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int k = (int)((__float_as_uint(acc[i][jx][r]) & keep) |
+                                        (uint32_t)((tl << 6) | (i << 4) | r));
+                    top[jx][3] = med3i(top[jx][2], top[jx][3], k);
+                    top[jx][2] = med3i(top[jx][1], top[jx][2], k);
+                    top[jx][1] = med3i(top[jx][0], top[jx][1], k);
+                    top[jx][0] = min(top[jx][0], k);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+    };
+    auto mfma_half = [&](const i32x4_t (&f)[FX], const i32x4_t (&e)[NEL], int ks) {
+#pragma unroll
+        for (int i = 0; i < FE; ++i)
+#pragma unroll
+            for (int jx = 0; jx < FX; ++jx)
+                acc[i][jx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, e[2 * i + ks]),
+                                                                    __builtin_bit_cast(bf16x8_t, f[jx]), acc[i][jx],
+                                                                    0, 0, 0);
+    };
+    auto mfma_first = [&](const i32x4_t (&f)[FX], const i32x4_t (&e)[NEL]) {
+        const f32x16_t z = {};
+#pragma unroll
+        for (int i = 0; i < FE; ++i)
+#pragma unroll
+            for (int jx = 0; jx < FX; ++jx)
+                acc[i][jx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, e[2 * i]),
+                                                                    __builtin_bit_cast(bf16x8_t, f[jx]), z, 0, 0, 0);
+    };
+
+    // Chunk g: X(g) sits in LDS buffer g % 2, X(g + 1) in registers, E(g)
+    // and E(g + 1) in registers.  The first half of g's products is followed
+    // by the loads of E(g + 2), the store of X(g + 1) into the other buffer
+    // and the load of X(g + 2); the barrier publishes X(g + 1), whose first
+    // fragments are read before the second half.  Past the last chunk the
+    // loads repeat in-bounds chunks that nobody uses, so every chunk issues
+    // the same loads and the compiler's counts stay exact.
+    if (total > 0) {  // a part past the last codeword has no tiles
+        const int last = total - 1;
+        i32x4_t e0[NEL], e1[NEL], e2[NEL], xr[NX];
+        int x_kc = 0;  // chunk within the tile of the X chunk in xr
+        load_x(0, xr);
+        load_e(0, e0);
+        load_e(min(1, last), e1);
+        store_x(0, xr);
+        x_kc = nkc > 1 ? 1 : 0;
+        load_x(x_kc, xr);
+        __syncthreads();
+        i32x4_t f0[FX], f1[FX];
+        read_frags(0, 0, f0);
+        int tl = 0, kc = 0, b = 0;
+        auto chunk = [&](int g, i32x4_t (&ec)[NEL], i32x4_t (&el)[NEL]) {
+            read_frags(b, 1, f1);
+            if (kc == 0) mfma_first(f0, ec);
+            else mfma_half(f0, ec, 0);
+            load_e(min(g + 2, last), el);
+            store_x(b ^ 1, xr);
+            x_kc = x_kc == nkc - 1 ? 0 : x_kc + 1;
+            load_x(x_kc, xr);
+            __syncthreads();
+            b ^= 1;
+            read_frags(b, 0, f0);
+            mfma_half(f1, ec, 1);
+            if (++kc == nkc) {
+                if constexpr (CONF) tile_lse();
+                tile_top4(tl);
+                kc = 0;
+                ++tl;
+            }
+        };
+        int g = 0;
+        for (; g + 3 <= total; g += 3) {
+            chunk(g, e0, e2);
+            chunk(g + 1, e1, e0);
+            chunk(g + 2, e2, e1);
+        }
+        if (g < total) chunk(g, e0, e2);
+        if (g + 1 < total) chunk(g + 1, e1, e0);
+    }
+    __syncthreads();
+
+    // merge: row x LISTS lists (wn, hf) x 4 candidates
+    int2* mc = reinterpret_cast<int2*>(qbuf);
+    const uint32_t pos_mask = (1u << seq_bits) - 1u;
+#pragma unroll
+    for (int jx = 0; jx < FX; ++jx) {
+        const int row = 32 * jx + fr;
+        const int list = 2 * wn + hf;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = top[jx][q];
+            const uint32_t s = (uint32_t)k & pos_mask;
+            const int c = c_part + (int)(s >> 6) * COLS + wn * 32 * FE + 32 * (int)((s >> 4) & 3) +
+                          8 * (int)((s >> 2) & 3) + 4 * hf + (int)(s & 3);
+            const bool ok = k != 0x7FFFFFFF && c < K;
+            mc[(row * LISTS + list) * 4 + q] = make_int2(ok ? (int)((uint32_t)k & keep) : 0x7FFFFFFF, ok ? c : -1);
+        }
+    }
+    __syncthreads();
+    for (int row = t; row < rows_here; row += C::THREADS) {
+        int bk[4] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
+        int bc[4] = {-1, -1, -1, -1};
+        for (int e = 0; e < LISTS * 4; ++e) {
+            const int2 v = mc[row * LISTS * 4 + e];
+            int k = v.x, c = v.y;
+#pragma unroll
+            for (int q = 3; q >= 0; --q)
+                if (cand_before(k, c, bk[q], bc[q])) {
+                    const int tk = bk[q], tc = bc[q];
+                    bk[q] = k; bc[q] = c; k = tk; c = tc;
+                }
+        }
+        int2* out = cand + ((r0 + row) * parts + p) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = make_int2(bk[q], bc[q]);
+    }
+    if constexpr (CONF) {
+        float2* ml = reinterpret_cast<float2*>(mc + ROWS * LISTS * 4);
+#pragma unroll
+        for (int jx = 0; jx < FX; ++jx) ml[(32 * jx + fr) * LISTS + 2 * wn + hf] = make_float2(lm[jx], ls[jx]);
+        __syncthreads();
+        for (int row = t; row < rows_here; row += C::THREADS) {
+            float m = -INFINITY;
+            for (int e = 0; e < LISTS; ++e) m = fmaxf(m, ml[row * LISTS + e].x);
+            float sum = 0.f;
+            for (int e = 0; e < LISTS; ++e) {
+                const float2 q = ml[row * LISTS + e];
+                if (q.x > -INFINITY) sum += q.y * __expf(q.x - m);
+            }
+            lse[(r0 + row) * parts + p] = make_float2(m, sum);
+        }
+    }
+}
+
 template <bool V4, bool CONF>
 __global__ void __launch_bounds__(256) vq_rescore_kernel(const float* __restrict__ X, int64_t N, int D,
                                                         const float* __restrict__ E, int K,
@@ -1149,7 +1426,7 @@ extern "C" xgs_status xgs_vq_candidates(int64_t N, int32_t D, int32_t K, void* w
     if (xgs_status s = vq_bf16_setup("xgs_vq_candidates", N, D, K, ws, ws_bytes, &plan, &w)) return s;
     if (N == 0) return XGS_OK;
     const int64_t blocks = ((N + VqCfg::ROWS - 1) / VqCfg::ROWS + 7) / 8 * 8 * plan.parts;
-    hipLaunchKernelGGL((vq_gemm_kernel<VqCfg, false>), dim3((unsigned)blocks), dim3(VqCfg::THREADS), 0, (hipStream_t)stream, w.xa, N,
+    hipLaunchKernelGGL((vq_gemm_ereg_kernel<VqRegCfg, false>), dim3((unsigned)blocks), dim3(VqRegCfg::THREADS), 0, (hipStream_t)stream, w.xa, N,
                        vq_dp(D) + Q_BK, w.ea, K, plan.parts, plan.tiles_part, plan.seq_bits, w.cand, 0.f, nullptr);
     return check_launch("xgs_vq_candidates");
 }

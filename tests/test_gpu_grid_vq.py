@@ -99,6 +99,25 @@ def test_vq_staged_calls_equal_assign(xgs):
     assert adj >= 0.999, (raw, adj)
 
 
+@pytest.mark.parametrize("n,d,k", [(816_000, 768, 4096), (2_037, 40, 4_400), (1000, 48, 77), (3001, 256, 520)])
+def test_vq_two_sweeps_agree_bitwise(xgs, n, d, k):
+    """The plain assignment's sweep (codeword operand in registers) and the
+    confidence form's sweep (both operands through LDS) form the same
+    products in the same order, so their candidates, and hence the rescored
+    index and distance, are bitwise equal: at the workload shape, with K over
+    two parts and a ragged row tail, with a part past the last codeword, and
+    with D not a multiple of 32 in the staged layout."""
+    X, E = vq_case(n, d, k, 256 if n > 100_000 else 16, seed=17)
+    Xg, Eg = t(X), t(E)
+    Eb, en = xgs.xgs_vq_prepare(Eg)
+    idx_a, dist_a = xgs.xgs_vq_assign(Xg, Eg, Eb, en, xgs.VQ_BF16_RESCORE4)
+    idx_c, dist_c, conf = xgs.xgs_vq_assign_conf(Xg, Eg, Eb, en, 0.7)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(np_(idx_a), np_(idx_c))
+    np.testing.assert_array_equal(np_(dist_a), np_(dist_c))
+    assert np.all(np_(conf) > 0)
+
+
 def test_vq_prepare_is_bf16_rounding(xgs):
     E = synth.vq_codebook(64, 32, 8, seed=9, centre_seed=8)
     Eb, en = xgs.xgs_vq_prepare(t(E))
