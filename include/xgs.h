@@ -307,6 +307,19 @@ xgs_status xgs_grid_sample(const float* P, int32_t D, int32_t Hf, int32_t Wf, in
                            int32_t W, int32_t stride, int32_t off_y, int32_t off_x, int32_t mode,
                            float* G, uint8_t* V, xgs_stream_t stream);
 
+/* The targets of every grid offset of one stride in one launch (App. D,
+ * Eq. (sampled_loc) over all (off_y, off_x) in [0, stride)^2; the device
+ * form of the per-offset target prefetch of Sec. 3.2.2): grid
+ * o = off_y * stride + off_x is bitwise what xgs_grid_sample writes for that
+ * offset.  G [stride^2][D][H_s][W_s], V [stride^2][H_s][W_s] (V may be NULL),
+ * H_s = ceil(H / stride), W_s = ceil(W / stride).  stride <=
+ * XGS_GRID_MAX_STRIDE, else XGS_ERR_UNSUPPORTED; other errors as
+ * xgs_grid_sample. */
+enum { XGS_GRID_MAX_STRIDE = 64 };
+xgs_status xgs_grid_sample_offsets(const float* P, int32_t D, int32_t Hf, int32_t Wf, int32_t H,
+                                   int32_t W, int32_t stride, int32_t mode, float* G, uint8_t* V,
+                                   xgs_stream_t stream);
+
 /* ----------------------------------------- f2: camera-pose gradient (Eq. (tracking))
  * dL/dxi for the left perturbation T(xi) = exp(xi^) T of the world-to-camera
  * pose, xi = (rho, phi) (translation, rotation), at xi = 0:

@@ -34,7 +34,7 @@ __all__ = [
     "XgsError", "Gaussians", "Projected", "Binning", "camera", "camera_from", "grid_dims",
     "xgs_project", "xgs_project_posed", "alloc_binning", "xgs_tile_sort", "xgs_tile_sort_noalloc", "xgs_render_fwd",
     "xgs_render_bwd", "xgs_render_bwd_zero",
-    "xgs_grid_sample", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_stage", "xgs_vq_candidates", "xgs_vq_rescore",
+    "xgs_grid_sample", "xgs_grid_sample_offsets", "xgs_vq_prepare", "xgs_vq_assign", "xgs_vq_stage", "xgs_vq_candidates", "xgs_vq_rescore",
     "vq_assign_workspace", "xgs_vq_ema_update", "xgs_semantic_softmax", "xgs_semantic_softmax_bwd",
     "xgs_semantic_loss", "semantic_step", "xgs_pose_grad", "xgs_tracking_loss", "tracking_step", "xgs_region_targets",
     "xgs_occluder_mask", "xgs_vq_assign_conf", "xgs_vq_ema_update_robust", "render", "BatchLayout",
@@ -356,6 +356,20 @@ def xgs_grid_sample(P: torch.Tensor, H: int, W: int, stride: int = 1, off_y: int
     V = V if V is not None else torch.empty((hs, ws), dtype=torch.uint8, device=P.device)
     check(lib.xgs_grid_sample(_ptr(P), D, Hf, Wf, int(H), int(W), int(stride), int(off_y), int(off_x), int(mode),
                               _ptr(G), _ptr(V), _stream(stream)), "xgs_grid_sample")
+    return G, V
+
+
+def xgs_grid_sample_offsets(P: torch.Tensor, H: int, W: int, stride: int, mode: int = GRID_BILINEAR, G=None, V=None,
+                            stream=None):
+    """Every offset's grid of one stride in one launch: G [s*s, D, hs, ws],
+    V [s*s, hs, ws]; grid oy * s + ox equals xgs_grid_sample(..., oy, ox)."""
+    D, Hf, Wf = P.shape
+    hs, ws = -(-H // stride), -(-W // stride)
+    n = stride * stride
+    G = G if G is not None else torch.empty((n, D, hs, ws), dtype=torch.float32, device=P.device)
+    V = V if V is not None else torch.empty((n, hs, ws), dtype=torch.uint8, device=P.device)
+    check(lib.xgs_grid_sample_offsets(_ptr(P), D, Hf, Wf, int(H), int(W), int(stride), int(mode), _ptr(G), _ptr(V),
+                                      _stream(stream)), "xgs_grid_sample_offsets")
     return G, V
 
 

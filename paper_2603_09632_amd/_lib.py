@@ -76,6 +76,8 @@ SIGNATURES = {
                                  c_void_p, c_size_t, c_void_p]),
     "xgs_grid_sample": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32,
                                   c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "xgs_grid_sample_offsets": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32,
+                                          c_int32, c_void_p, c_void_p, c_void_p]),
     "xgs_vq_assign_workspace": (c_size_t, [c_int64, c_int32, c_int32, c_int32]),
     "xgs_vq_prepare": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "xgs_vq_assign": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_int32,

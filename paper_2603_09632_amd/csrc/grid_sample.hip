@@ -59,12 +59,21 @@ __device__ __forceinline__ float sample(const float* __restrict__ Pd, int Wf, co
 // channels per thread: the source coordinates of a pixel are computed once per chunk
 constexpr int kChanChunk = 32;
 
-template <bool VEC, typename I>
+// ALL: blockIdx.z is the grid offset o = oy s + ox, whose grid goes to
+// G + o D Hs Ws and V + o Hs Ws (the oy, ox arguments are ignored).
+template <bool VEC, typename I, bool ALL>
 __global__ void __launch_bounds__(256) grid_sample_kernel(const float* __restrict__ P, int D, int Hf,
                                                          int Wf, int H, int W, int s, int oy, int ox,
                                                          int mode, int Hs, int Ws,
                                                          float* __restrict__ G, uint8_t* __restrict__ V) {
     const int64_t hw = (int64_t)Hs * Ws;
+    if constexpr (ALL) {
+        const int o = blockIdx.z;
+        oy = o / s;
+        ox = o - oy * s;
+        G += (int64_t)o * D * hw;
+        if (V) V += (int64_t)o * hw;
+    }
     const int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     if (p0 >= hw) return;
     Src src[4];
@@ -134,38 +143,79 @@ __global__ void __launch_bounds__(256) grid_sample_kernel(const float* __restric
 
 using namespace xgs;
 
-extern "C" xgs_status xgs_grid_sample(const float* P, int32_t D, int32_t Hf, int32_t Wf, int32_t H,
-                                      int32_t W, int32_t stride, int32_t off_y, int32_t off_x,
-                                      int32_t mode, float* G, uint8_t* V, xgs_stream_t stream) {
-    clear_error();
+// Checks shared by both entry points; fills the grid shape and launch mode.
+static xgs_status grid_setup(const char* who, const float* P, int32_t D, int32_t Hf, int32_t Wf, int32_t H,
+                             int32_t W, int32_t stride, int32_t mode, const float* G, int64_t* hw_out, int* Hs_out,
+                             int* Ws_out, bool* i32_out) {
+    const std::string w = who;
     if (D < 0 || Hf < 1 || Wf < 1 || H < 1 || W < 1 || stride < 1)
-        return fail(XGS_ERR_INVALID_ARG, "xgs_grid_sample: sizes must be positive (D >= 0)");
-    if (off_y < 0 || off_x < 0 || off_y >= stride || off_x >= stride)
-        return fail(XGS_ERR_INVALID_ARG, "xgs_grid_sample: offsets must lie in [0, stride)");
-    if (mode != XGS_GRID_BILINEAR && mode != XGS_GRID_NEAREST)
-        return fail(XGS_ERR_INVALID_ARG, "xgs_grid_sample: unknown mode");
+        return fail(XGS_ERR_INVALID_ARG, w + ": sizes must be positive (D >= 0)");
+    if (mode != XGS_GRID_BILINEAR && mode != XGS_GRID_NEAREST) return fail(XGS_ERR_INVALID_ARG, w + ": unknown mode");
     if ((int64_t)Hf * Wf * D >= (int64_t(1) << 31))
-        return fail(XGS_ERR_UNSUPPORTED, "xgs_grid_sample: feature map above 2^31 elements");
+        return fail(XGS_ERR_UNSUPPORTED, w + ": feature map above 2^31 elements");
     const int Hs = (H + stride - 1) / stride, Ws = (W + stride - 1) / stride;
+    if (D > 0 && (!P || !G)) return fail(XGS_ERR_INVALID_ARG, w + ": null P or G");
+    if ((D + kChanChunk - 1) / kChanChunk > 65535) return fail(XGS_ERR_UNSUPPORTED, w + ": too many channels");
+    // 32-bit source arithmetic when every intermediate fits: p < hw, u < H + stride,
+    // u (Hf - 1) and v (Wf - 1), and the doubled remainders
     const int64_t hw = (int64_t)Hs * Ws;
-    if (D > 0 && (!P || !G)) return fail(XGS_ERR_INVALID_ARG, "xgs_grid_sample: null P or G");
-    if (D == 0 && !V) return XGS_OK;
+    const int64_t lim = (int64_t(1) << 30);
+    *i32_out = hw < lim && (int64_t)(H + stride) * Hf < lim && (int64_t)(W + stride) * Wf < lim;
+    *hw_out = hw;
+    *Hs_out = Hs;
+    *Ws_out = Ws;
+    return XGS_OK;
+}
+
+template <bool ALL>
+static void grid_launch(const float* P, int32_t D, int32_t Hf, int32_t Wf, int32_t H, int32_t W, int32_t stride,
+                        int32_t off_y, int32_t off_x, int32_t mode, int Hs, int Ws, int64_t hw, bool i32, float* G,
+                        uint8_t* V, unsigned grids, hipStream_t st) {
     const bool vec = (hw % 4 == 0) && aligned(G, 16);
     const unsigned bx = (unsigned)((hw + 1023) / 1024);
     const unsigned by = (unsigned)(D > 0 ? (D + kChanChunk - 1) / kChanChunk : 1);
-    if (by > 65535) return fail(XGS_ERR_UNSUPPORTED, "xgs_grid_sample: too many channels");
-    hipStream_t st = (hipStream_t)stream;
-    // 32-bit source arithmetic when every intermediate fits: p < hw, u < H + stride,
-    // u (Hf - 1) and v (Wf - 1), and the doubled remainders
-    const int64_t lim = (int64_t(1) << 30);
-    const bool i32 = hw < lim && (int64_t)(H + stride) * Hf < lim && (int64_t)(W + stride) * Wf < lim;
-#define XGS_GS_LAUNCH(V4, I)                                                                         \
-    hipLaunchKernelGGL((grid_sample_kernel<V4, I>), dim3(bx, by), dim3(256), 0, st, P, D, Hf, Wf, H, W, \
-                       stride, off_y, off_x, mode, Hs, Ws, G, V)
+    const dim3 grid(bx, by, grids);
+#define XGS_GS_LAUNCH(V4, I)                                                                               \
+    hipLaunchKernelGGL((grid_sample_kernel<V4, I, ALL>), grid, dim3(256), 0, st, P, D, Hf, Wf, H, W, stride, \
+                       off_y, off_x, mode, Hs, Ws, G, V)
     if (vec && i32) XGS_GS_LAUNCH(true, int32_t);
     else if (vec) XGS_GS_LAUNCH(true, int64_t);
     else if (i32) XGS_GS_LAUNCH(false, int32_t);
     else XGS_GS_LAUNCH(false, int64_t);
 #undef XGS_GS_LAUNCH
+}
+
+extern "C" xgs_status xgs_grid_sample(const float* P, int32_t D, int32_t Hf, int32_t Wf, int32_t H,
+                                      int32_t W, int32_t stride, int32_t off_y, int32_t off_x,
+                                      int32_t mode, float* G, uint8_t* V, xgs_stream_t stream) {
+    clear_error();
+    int64_t hw;
+    int Hs, Ws;
+    bool i32;
+    if (xgs_status s = grid_setup("xgs_grid_sample", P, D, Hf, Wf, H, W, stride, mode, G, &hw, &Hs, &Ws, &i32))
+        return s;
+    if (off_y < 0 || off_x < 0 || off_y >= stride || off_x >= stride)
+        return fail(XGS_ERR_INVALID_ARG, "xgs_grid_sample: offsets must lie in [0, stride)");
+    if (D == 0 && !V) return XGS_OK;
+    grid_launch<false>(P, D, Hf, Wf, H, W, stride, off_y, off_x, mode, Hs, Ws, hw, i32, G, V, 1u,
+                       (hipStream_t)stream);
     return check_launch("xgs_grid_sample");
+}
+
+extern "C" xgs_status xgs_grid_sample_offsets(const float* P, int32_t D, int32_t Hf, int32_t Wf, int32_t H,
+                                              int32_t W, int32_t stride, int32_t mode, float* G, uint8_t* V,
+                                              xgs_stream_t stream) {
+    clear_error();
+    if (stride > XGS_GRID_MAX_STRIDE)
+        return fail(XGS_ERR_UNSUPPORTED, "xgs_grid_sample_offsets: stride above XGS_GRID_MAX_STRIDE");
+    int64_t hw;
+    int Hs, Ws;
+    bool i32;
+    if (xgs_status s = grid_setup("xgs_grid_sample_offsets", P, D, Hf, Wf, H, W, stride, mode, G, &hw, &Hs, &Ws,
+                                  &i32))
+        return s;
+    if (D == 0 && !V) return XGS_OK;
+    grid_launch<true>(P, D, Hf, Wf, H, W, stride, 0, 0, mode, Hs, Ws, hw, i32, G, V,
+                      (unsigned)(stride * stride), (hipStream_t)stream);
+    return check_launch("xgs_grid_sample_offsets");
 }

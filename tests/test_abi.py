@@ -61,6 +61,12 @@ def test_invalid_arguments_are_rejected_before_launch(xgs):
     assert st == 1 and b"offsets" in lib.xgs_last_error()
     st = lib.xgs_grid_sample(None, 4, 3, 3, 10, 10, 1, 0, 0, 7, None, None, None)
     assert st == 1 and b"mode" in lib.xgs_last_error()
+    st = lib.xgs_grid_sample_offsets(None, 4, 3, 3, 10, 10, 2, 7, None, None, None)
+    assert st == 1 and b"mode" in lib.xgs_last_error()
+    st = lib.xgs_grid_sample_offsets(None, 4, 3, 3, 1000, 1000, 65, 0, None, None, None)
+    assert st == 4 and b"stride" in lib.xgs_last_error()
+    st = lib.xgs_grid_sample_offsets(None, 4, 3, 3, 10, 10, 0, 0, None, None, None)
+    assert st == 1
     st = lib.xgs_vq_assign(None, 10, 20, None, None, None, 4, 1, None, None, None, 0, None)
     assert st == 1
     st = lib.xgs_vq_ema_update(None, None, 5, 4, 4, None, None, None, None, None, None, 1.5, 1e-5, 1, None, 0, None)

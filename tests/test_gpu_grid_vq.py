@@ -40,6 +40,35 @@ def test_grid_sample(xgs, H, W, Hf, Wf, D, stride, oy, ox):
             assert rel_max(np_(G), Gr) < 1e-6
 
 
+@pytest.mark.parametrize("H,W,Hf,Wf,D,stride,mode", [
+    (480, 640, 30, 40, 64, 2, 0),        # the mapping-scale map, four offsets
+    (96, 128, 7, 9, 13, 3, 0),           # ragged grids (H_s W_s not a multiple of 4)
+    (50, 70, 13, 5, 6, 4, 1),            # nearest, padded rows and columns
+    (17, 1, 4, 1, 3, 2, 0),              # degenerate width
+])
+def test_grid_sample_all_offsets(xgs, H, W, Hf, Wf, D, stride, mode):
+    """Every offset's grid in one launch is bitwise the per-offset call, and
+    matches the oracle for each offset."""
+    P = synth.feature_map(D, Hf, Wf, seed=7)
+    Pg = t(P)
+    G, V = xgs.xgs_grid_sample_offsets(Pg, H, W, stride, mode)
+    torch.cuda.synchronize()
+    G, V = np_(G), np_(V)
+    for oy in range(stride):
+        for ox in range(stride):
+            o = oy * stride + ox
+            g1, v1 = xgs.xgs_grid_sample(Pg, H, W, stride, oy, ox, mode)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(G[o], np_(g1))
+            np.testing.assert_array_equal(V[o], np_(v1))
+            ref, vref = oracle.grid_sample(P, H, W, stride, oy, ox, mode)
+            np.testing.assert_array_equal(V[o], vref)
+            if mode == xgs.GRID_NEAREST:
+                np.testing.assert_array_equal(G[o], ref)
+            else:
+                assert rel_max(G[o], ref) < 1e-6
+
+
 def test_grid_sample_affine_exact(xgs):
     P = synth.affine_feature_map(5, 9, 17)
     G, _ = xgs.xgs_grid_sample(t(P), 65, 65)
