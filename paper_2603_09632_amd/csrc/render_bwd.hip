@@ -45,7 +45,6 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
     constexpr int CH = 4 + CS;
     constexpr int CHP = (CH + 3) / 4 * 4;           // LDS row stride (float4 rows)
     constexpr int NT = (CH + 15) / 16;
-    constexpr int PER = (16 * CHP + 63) / 64;       // channel values per lane per batch
     constexpr int VG = 6;
     __shared__ float wl[64 * 17];
     __shared__ Ring ring;
@@ -132,17 +131,47 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
             fetch(cpos);
         }
     };
-    float cv[PER];
+    // Channel rows of a batch (only the S = C G^T product reads them): the
+    // colour and depth of splat lane / 4 (channel lane % 4) in one load, then
+    // the feature rows as 64 consecutive (splat, feature) pairs per load, so
+    // that every load reads one array and feature rows are read contiguously.
+    // Slots past the batch hold zeros.
+    constexpr int PERF = (16 * CS + 63) / 64;
+    constexpr int CSD = CS > 0 ? CS : 1;  // divisor (no feature loads when CS = 0)
+    float cv[GEO ? 1 + PERF : 1];
     auto fetch_channels = [&](int base, int n) {
+        if constexpr (GEO) {
+            {
+                const int k = lane >> 2, c = lane & 3;
+                const int gk = k < n ? ring.gid[(base + k) & (kRing - 1)] : -1;
+                const uint32_t i = (uint32_t)(gk >= 0 ? gk : 0);
+                const float* src = c < 3 ? colors + 3 * (size_t)i + c
+                                         : reinterpret_cast<const float*>(splat) + 8 * (size_t)i + 6;  // depth
+                cv[0] = gk >= 0 ? *src : 0.f;
+            }
 #pragma unroll
-        for (int t = 0; t < PER; ++t) {
-            const int e = lane + 64 * t;
-            const int k = e / CHP, c = e - k * CHP;
-            const int gk = (e < 16 * CHP && k < n) ? ring.gid[(base + k) & (kRing - 1)] : -1;
-            cv[t] = (gk >= 0 && c < CH && (EXACT || c < 4 + csem))
-                        ? channel_of<CS, EXACT>(colors, splat, features, csem, (uint32_t)gk, c) : 0.f;
+            for (int t = 1; t <= PERF; ++t) {
+                const int e = lane + 64 * (t - 1);
+                const int k = e / CSD, f = e - k * CSD;
+                const int gk = k < n ? ring.gid[(base + k) & (kRing - 1)] : -1;
+                cv[t] = (gk >= 0 && (EXACT || f < csem)) ? features[(size_t)gk * fstride + f] : 0.f;
+            }
         }
     };
+    auto store_channels = [&]() {
+        if constexpr (GEO) {
+            chl[(lane >> 2) * CHP + (lane & 3)] = cv[0];
+#pragma unroll
+            for (int t = 1; t <= PERF; ++t) {
+                const int e = lane + 64 * (t - 1);
+                const int k = e / CSD, f = e - k * CSD;
+                if (k < 16) chl[k * CHP + 4 + f] = cv[t];
+            }
+        }
+    };
+    if constexpr (GEO && CHP > CH) {  // padding columns, read as zeros by the product
+        for (int i = lane; i < 16 * (CHP - CH); i += 64) chl[(i / (CHP - CH)) * CHP + CH + i % (CHP - CH)] = 0.f;
+    }
     fetch(top);
     fill();
     __syncthreads();
@@ -150,11 +179,7 @@ __global__ void __launch_bounds__(64) render_bwd_mfma_kernel(
     fetch_channels(head, nb);
     float S = 0.f;
     while (nb > 0) {
-#pragma unroll
-        for (int t = 0; t < PER; ++t) {
-            const int e = lane + 64 * t;
-            if (e < 16 * CHP) chl[e] = cv[t];
-        }
+        store_channels();
         fill();
         __syncthreads();
         if constexpr (GEO) {
