@@ -38,7 +38,7 @@ namespace xgs {
 // tile.  Splat records are indexed by global Gaussian index, colours and
 // features by index within the slot's scene.
 template <int CS, bool EXACT, bool BATCH = false>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) render_fwd_mfma_kernel(
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CS > 32 ? 3 : 4))) render_fwd_mfma_kernel(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float4* __restrict__ splat, const float* __restrict__ colors,
     const float* __restrict__ features, int csem, TileGrid g, float* __restrict__ out,
@@ -76,6 +76,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) re
     if (P.tile >= g.tiles) return;
     const QuadRect qr = quad_rect(g, P);
     const int lane = threadIdx.x;
+    // The first 16 channels of a splat (colour, depth, features 0-11) as one
+    // lane-constant source and stride: channel lane % 16 of Gaussian i is
+    // src0[i * str0], so that the batch's loads of those channels do not
+    // branch on the channel.
+    const int fstr = EXACT ? CS : csem;
+    const int j0 = lane & 15;
+    const float* const src0 = j0 < 3 ? colors + j0
+                                     : j0 == 3 ? reinterpret_cast<const float*>(splat) + 6 : features + (j0 - 4);
+    const int str0 = j0 < 3 ? 3 : j0 == 3 ? 8 : fstr;
     f32x4_t acc[4][NT];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -119,8 +128,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) re
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int c = 16 * nt + (lane & 15);
-                b[kk][nt] = (gs >= 0 && c < CH && (EXACT || c < 4 + csem))
-                                ? channel_of<CS, EXACT>(colors, splat, features, csem, (uint32_t)gs, c) : 0.f;
+                const bool use = gs >= 0 && c < CH && (EXACT || c < 4 + csem);
+                if (nt == 0)
+                    b[kk][nt] = use ? src0[(size_t)(uint32_t)gs * str0] : 0.f;
+                else
+                    b[kk][nt] = use ? features[(size_t)(uint32_t)gs * fstr + (c - 4)] : 0.f;
             }
         }
         // Branch-free per splat (selects only), so that the next splats' ring
