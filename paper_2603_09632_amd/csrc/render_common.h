@@ -148,16 +148,6 @@ __device__ __forceinline__ f32x4_t mfma16x16x4(float a, float b, f32x4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Channel c of Gaussian i: 0..2 colour, 3 camera depth (from the splat
-// record), 4.. semantic features.
-template <int CS, bool EXACT>
-__device__ __forceinline__ float channel_of(const float* __restrict__ colors, const float4* __restrict__ splat,
-                                            const float* __restrict__ features, int csem, uint32_t i, int c) {
-    if (c < 3) return colors[3 * (size_t)i + c];
-    if (c == 3) return splat[2 * (size_t)i + 1].z;
-    return features[(size_t)i * (EXACT ? CS : csem) + (c - 4)];
-}
-
 // Wave-uniform value: the compiler keeps it in a scalar register, so loads
 // indexed by it become scalar (constant-cache) loads.
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
