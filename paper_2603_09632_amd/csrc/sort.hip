@@ -80,12 +80,17 @@ __global__ void __launch_bounds__(256) scan_reduce_kernel(const uint32_t* __rest
         for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < zero_n; i += (int64_t)gridDim.x * 256)
             zero_p[i] = 0u;
     int64_t base = (int64_t)blockIdx.x * kScanItems;
-    uint64_t s = 0;
+    // every load is issued before the first add (a guarded add per load would
+    // wait for each load in turn)
+    uint32_t v[kScanItems / 256];
 #pragma unroll
     for (int r = 0; r < kScanItems / 256; ++r) {
-        int64_t i = base + r * 256 + threadIdx.x;
-        if (i < n) s += in[i];
+        const int64_t i = base + r * 256 + threadIdx.x;
+        v[r] = i < n ? in[i] : 0u;
     }
+    uint64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems / 256; ++r) s += v[r];
     uint64_t incl = block_incl_scan_256(s, sh);
     if (threadIdx.x == 255) partials[blockIdx.x] = incl;
 }
@@ -233,11 +238,19 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t
     const int64_t base = (int64_t)blockIdx.x * kSortItems;
     if (base >= m) return;  // uniform: a column no scan reads
     h[threadIdx.x] = 0;
+    // all of the block's keys are loaded before any is counted (a load per
+    // count would wait a full memory latency each)
+    uint64_t k[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + r * kSortThreads + threadIdx.x;
+        k[r] = i < m ? keys[i] : 0ull;
+    }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        int64_t i = base + r * kSortThreads + threadIdx.x;
-        if (i < m) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
+        const int64_t i = base + r * kSortThreads + threadIdx.x;
+        if (i < m) atomicAdd(&h[(uint32_t)(k[r] >> shift) & mask], 1u);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
@@ -301,6 +314,16 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     const int64_t base = (int64_t)blockIdx.x * kSortItems;
     if (base >= m) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // every round's pair is loaded up front: a load issued per round would
+    // put a full memory latency between consecutive rounds
+    uint64_t rkey[kSortRounds];
+    uint32_t rval[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + r * kSortThreads + t;
+        rkey[r] = i < m ? kin[i] : 0ull;
+        rval[r] = i < m ? vin[i] : 0u;
+    }
     {
         const uint32_t tv = totals[t];
         const uint32_t incl = wave_incl_scan(tv, lane);
@@ -312,12 +335,13 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
         goff[t] = pre + incl - tv + hist[(int64_t)t * gridDim.x + blockIdx.x];
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         int64_t i = base + r * kSortThreads + t;
         if (base + r * kSortThreads >= m) break;  // uniform across the block
         bool valid = i < m;
-        uint64_t key = valid ? kin[i] : 0ull;
-        uint32_t val = valid ? vin[i] : 0u;
+        const uint64_t key = rkey[r];
+        const uint32_t val = rval[r];
         uint32_t d = (uint32_t)(key >> shift) & mask;
 #pragma unroll
         for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
@@ -379,9 +403,12 @@ __global__ void ranges_kernel(const uint64_t* __restrict__ keys, const int64_t* 
     const int64_t m = *count;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    uint64_t s = keys[i] >> shift;
-    if (i == 0 || (keys[i - 1] >> shift) != s) ranges[2 * s] = (uint32_t)i;
-    if (i == m - 1 || (keys[i + 1] >> shift) != s) ranges[2 * s + 1] = (uint32_t)(i + 1);
+    // the three keys are loaded together (in-bounds neighbours, ignored at the ends)
+    const uint64_t s = keys[i] >> shift;
+    const uint64_t sp = keys[i > 0 ? i - 1 : i] >> shift;
+    const uint64_t sn = keys[i < m - 1 ? i + 1 : i] >> shift;
+    if (i == 0 || sp != s) ranges[2 * s] = (uint32_t)i;
+    if (i == m - 1 || sn != s) ranges[2 * s + 1] = (uint32_t)(i + 1);
 }
 
 xgs_status segment_ranges(const uint64_t* keys, const int64_t* count, int64_t cap, int shift,

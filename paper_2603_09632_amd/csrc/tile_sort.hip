@@ -37,6 +37,7 @@ __global__ void __launch_bounds__(256) emit_keys_kernel(
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x) + 64 * w;  // the wave's first Gaussian
     if (i0 >= n) return;  // uniform per wave
     const int64_t i = i0 + lane;
+    const uint64_t base = offsets[i0];  // issued with the count load
     uint32_t cnt = 0;
     uint2 r = make_uint2(0u, 0u);
     uint32_t dbits = 0;
@@ -61,7 +62,6 @@ __global__ void __launch_bounds__(256) emit_keys_kernel(
     s_dbits[w][lane] = dbits;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const uint64_t base = offsets[i0];
     for (uint32_t t = lane; t < total; t += 64) {
         const uint64_t pos = base + t;
         if (pos >= (uint64_t)cap) break;  // positions only grow along the loop
