@@ -277,9 +277,21 @@ __global__ void __launch_bounds__(256) radix_scan_kernel(uint32_t* __restrict__ 
     const int64_t m = *count;
     const int64_t nbe = m <= 0 ? 0 : min(nb, (m + kSortItems - 1) / kSortItems);
     uint32_t carry = 0;
+    // the first four chunks of the row are loaded together
+    constexpr int PRE = 4;
+    uint32_t pv[PRE];
+#pragma unroll
+    for (int c = 0; c < PRE; ++c) {
+        const int64_t i = (int64_t)c * 256 + t;
+        pv[c] = i < nbe ? row[i] : 0u;
+    }
     for (int64_t b0 = 0; b0 < nbe; b0 += 256) {
         const int64_t i = b0 + t;
-        const uint32_t v = i < nbe ? row[i] : 0u;
+        uint32_t v = 0u;
+#pragma unroll
+        for (int c = 0; c < PRE; ++c)
+            if (b0 == (int64_t)c * 256) v = pv[c];
+        if (b0 >= (int64_t)PRE * 256) v = i < nbe ? row[i] : 0u;
         const uint32_t incl = wave_incl_scan(v, lane);
         if (lane == 63) ws[w] = incl;
         __syncthreads();
