@@ -419,12 +419,14 @@ def test_render_quadrant_culling_boundary(xgs, stride, oy, ox):
 
 
 
-@pytest.mark.parametrize("c_sem", [0, 5, 20, 40, 54])
+@pytest.mark.parametrize("c_sem", [0, 1, 3, 5, 20, 40, 54])
 def test_render_channel_counts(xgs, c_sem):
-    """Channel counts outside the common ones: none (RGB + depth only), counts
-    that run on a wider compiled width with the rest masked (5, 20, 40) and the
-    largest the geometric backward takes (54).  Staged forward and backward
-    against the oracle, and the feature-only backward against the full one."""
+    """Channel counts outside the common ones: none (RGB + depth only), exact
+    widths whose channel rows are padded to whole float4s in the backward
+    (1, 3), counts that run on a wider compiled width with the rest masked (5,
+    20, 40) and the largest the geometric backward takes (54).  Staged forward
+    and backward against the oracle, and the feature-only backward against the
+    full one."""
     scene = synth.tiny_scene(seed=11, n=1500, c_sem=c_sem)
     cam = synth.tiny_camera().with_grid(2, 1, 0) if c_sem % 2 else synth.tiny_camera()
     r, ref, amb = staged(xgs, scene, cam)
