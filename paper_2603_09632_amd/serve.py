@@ -36,6 +36,7 @@ from __future__ import annotations
 
 import collections
 import ctypes
+import gc
 import queue
 import threading
 import time
@@ -274,6 +275,27 @@ class Server:
             if self.use_graphs:
                 self._precapture(a)
 
+    @staticmethod
+    def _capture(body) -> "torch.cuda.CUDAGraph":
+        """Captures body() into a graph on the current stream.  Python's
+        garbage collector runs before and not during the capture: a collection
+        inside it could free a GPU tensor or event from this thread, a call the
+        capture forbids (the process aborts in the destructor)."""
+        gc.collect()
+        was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            graph = torch.cuda.CUDAGraph()
+            graph.capture_begin(capture_error_mode="thread_local")
+            try:
+                body()
+            finally:
+                graph.capture_end()
+        finally:
+            if was_enabled:
+                gc.enable()
+        return graph
+
     def _precapture(self, arena: _Arena):
         """Captures every capacity bucket's graph up front (on an all-empty
         slot table), so that no capture stalls a request later."""
@@ -284,13 +306,7 @@ class Server:
                 ctypes.memmove(arena.h_table.data_ptr(), full, ctypes.sizeof(full))
                 arena.d_table.copy_(arena.h_table, non_blocking=True)
                 arena.body(key)                      # first run eager
-                graph = torch.cuda.CUDAGraph()
-                graph.capture_begin(capture_error_mode="thread_local")
-                try:
-                    arena.body(key)
-                finally:
-                    graph.capture_end()
-                arena.graphs[key] = graph
+                arena.graphs[key] = self._capture(lambda: arena.body(key))
                 arena.uses[key] += 1
                 self.graphs_captured += 1
                 # the host table is rewritten for the next bucket only after
@@ -355,13 +371,7 @@ class Server:
                     # captured on the arena's stream on the bucket's second
                     # batch; the capture does not synchronise the device, so
                     # the other arena keeps running
-                    graph = torch.cuda.CUDAGraph()
-                    graph.capture_begin(capture_error_mode="thread_local")
-                    try:
-                        arena.body(key)
-                    finally:
-                        graph.capture_end()
-                    arena.graphs[key] = graph
+                    arena.graphs[key] = self._capture(lambda: arena.body(key))
                     self.graphs_captured += 1
                 arena.graphs[key].replay()
             else:
