@@ -309,33 +309,44 @@ __global__ void __launch_bounds__(256) radix_scan_kernel(uint32_t* __restrict__ 
     if (t == 0) totals[d] = carry;
 }
 
-// Stable scatter.  The block first turns the 256 digit totals into digit
-// bases (exclusive prefix) and adds its own offsets within each digit.  Items
-// are ranked in block order (round, wave, lane): a lane's rank among equal
-// digits in its wave comes from the digit's ballots, the per-wave counts are
-// prefixed through LDS, and a running per-digit base carries the order across
-// rounds.
+// Stable scatter.  Wavefront w of the block owns the contiguous run of
+// kSortRounds * 64 items that starts at base + w * kSortRounds * 64, so the
+// block order of equal digits is (wave, round, lane) and the waves only meet
+// twice.  Each wave first ranks every one of its items among the equal digits
+// of its round (the lanes whose digit ballots agree) and counts its digits into
+// its own LDS row; one barrier later thread t turns digit t's four wave
+// counts into the wave bases (the digit's global base from the totals and the
+// block's offset from the scanned histogram, plus the counts of the earlier
+// waves); a second barrier later every wave walks its rounds again in order,
+// each item going to its wave base plus its rank, the digit's first lane
+// moving that base on by the round's count.  LDS operations of one wave
+// complete in issue order, so a wave's own counter row needs no barrier.
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const int64_t* __restrict__ count, int shift, uint32_t mask,
     int nbits, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals) {
-    __shared__ uint32_t goff[256];
-    __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t ws[4];
+    constexpr int kWaves = kSortThreads / 64;
+    static_assert(kWaves == 4 && kSortRounds * 64 * kWaves == kSortItems, "four wavefronts per sort block");
+    __shared__ uint32_t run[kWaves][256];
+    __shared__ uint32_t ws[kWaves];
     const int64_t m = *count;
     const int64_t base = (int64_t)blockIdx.x * kSortItems;
     if (base >= m) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t wbase = base + (int64_t)w * (kSortRounds * 64) + lane;
     // every round's pair is loaded up front: a load issued per round would
     // put a full memory latency between consecutive rounds
     uint64_t rkey[kSortRounds];
     uint32_t rval[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        const int64_t i = base + r * kSortThreads + t;
+        const int64_t i = wbase + r * 64;
         rkey[r] = i < m ? kin[i] : 0ull;
         rval[r] = i < m ? vin[i] : 0u;
     }
+    // digit t's base for this block: exclusive prefix of the digit totals
+    // plus the block's offset among the keys with digit t
+    uint32_t g;
     {
         const uint32_t tv = totals[t];
         const uint32_t incl = wave_incl_scan(tv, lane);
@@ -343,45 +354,47 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
         __syncthreads();
         uint32_t pre = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) pre += k < w ? ws[k] : 0u;
-        goff[t] = pre + incl - tv + hist[(int64_t)t * gridDim.x + blockIdx.x];
+        for (int k = 0; k < kWaves; ++k) pre += k < w ? ws[k] : 0u;
+        g = pre + incl - tv + hist[(int64_t)t * gridDim.x + blockIdx.x];
     }
+#pragma unroll
+    for (int k = 0; k < 256 / 64; ++k) run[w][lane + 64 * k] = 0u;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // rank among the round's equal digits (bits 0-7) and, for the digit's
+    // first lane, the round's count of that digit (bits 8-15)
+    uint32_t rc[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        int64_t i = base + r * kSortThreads + t;
-        if (base + r * kSortThreads >= m) break;  // uniform across the block
-        bool valid = i < m;
-        const uint64_t key = rkey[r];
-        const uint32_t val = rval[r];
-        uint32_t d = (uint32_t)(key >> shift) & mask;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
-        __syncthreads();
+        const bool valid = wbase + r * 64 < m;
+        const uint32_t d = (uint32_t)(rkey[r] >> shift) & mask;
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < nbits; ++b) {
-            uint64_t bm = __ballot((d >> b) & 1u);
+            const uint64_t bm = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bm : ~bm;
         }
-        uint32_t rank = __popcll(peers & lt);
-        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
-        __syncthreads();
-        // thread t turns the 4 wave counts of digit t into exclusive offsets
-        uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
-        uint32_t g = goff[t];
-        __syncthreads();
-        wcnt[0][t] = g;
-        wcnt[1][t] = g + c0;
-        wcnt[2][t] = g + c0 + c1;
-        wcnt[3][t] = g + c0 + c1 + c2;
-        goff[t] = g + c0 + c1 + c2 + c3;
-        __syncthreads();
-        if (valid) {
-            uint32_t dst = wcnt[w][d] + rank;
-            kout[dst] = key;
-            vout[dst] = val;
+        const uint32_t rank = __popcll(peers & lt), cnt = __popcll(peers);
+        rc[r] = rank | (cnt << 8);
+        if (valid && rank == 0) atomicAdd(&run[w][d], cnt);
+    }
+    __syncthreads();
+    {
+        const uint32_t c0 = run[0][t], c1 = run[1][t], c2 = run[2][t];
+        run[0][t] = g;
+        run[1][t] = g + c0;
+        run[2][t] = g + c0 + c1;
+        run[3][t] = g + c0 + c1 + c2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        if (wbase + r * 64 < m) {
+            const uint32_t d = (uint32_t)(rkey[r] >> shift) & mask;
+            const uint32_t rank = rc[r] & 0xffu;
+            const uint32_t dst = run[w][d] + rank;
+            kout[dst] = rkey[r];
+            vout[dst] = rval[r];
+            if (rank == 0) atomicAdd(&run[w][d], rc[r] >> 8);
         }
-        __syncthreads();
     }
 }
 
