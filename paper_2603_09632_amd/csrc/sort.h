@@ -10,6 +10,16 @@ constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 8;     // rounds of 256 items per sort block (2, 4, 6, 12, 16 measured slower)
 constexpr int kSortItems = kSortThreads * kSortRounds;
 
+// Inclusive prefix sum of v over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
 inline int64_t scan_blocks(int64_t n) { return (n + kScanItems - 1) / kScanItems; }
 inline int64_t sort_blocks(int64_t cap) { return (cap + kSortItems - 1) / kSortItems; }
 

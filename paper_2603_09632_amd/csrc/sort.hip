@@ -256,15 +256,6 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t
     hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
-    }
-    return v;
-}
-
 // One workgroup per digit d: exclusive scan of d's per-block counts in place
 // (the offset of block b among the keys with digit d), and totals[d], over
 // the blocks that hold keys (row stride nb).

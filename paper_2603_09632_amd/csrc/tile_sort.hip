@@ -135,61 +135,67 @@ __device__ __forceinline__ uint64_t same_key_lanes(uint32_t key, uint64_t valid)
 
 __global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __restrict__ ranges, int T,
                                                          uint32_t* __restrict__ order) {
+    constexpr int kIters = kOrderMax / (kOrderWaves * 64);  // 64-tile steps per wavefront
     __shared__ uint32_t cnt[kOrderWaves][256];  // per wave and key: count, then next output slot
-    __shared__ uint32_t tot[256];
+    __shared__ uint32_t ws[4];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     for (int i = t; i < kOrderWaves * 256; i += 1024) (&cnt[0][0])[i] = 0;
-    __syncthreads();
     const int per = (T + kOrderWaves - 1) / kOrderWaves;
     const int lo = min(T, w * per), hi = min(T, lo + per);
     const uint64_t lt = (1ull << lane) - 1ull;
-    auto key_of = [&](int i) {
-        const uint32_t len = ranges[2 * i + 1] - ranges[2 * i];
-        return 255u - min(len >> 4, 255u);
-    };
-    for (int i0 = lo; i0 < hi; i0 += 64) {
-        const int i = i0 + lane;
-        const bool ok = i < hi;
-        const uint32_t key = ok ? key_of(i) : 0u;
-        const uint64_t m = same_key_lanes(key, __ballot(ok));
-        if (ok && (m & lt) == 0) cnt[w][key] += (uint32_t)__popcll(m);
+    // every key of the wavefront's range is loaded up front (in-bounds
+    // clamped reads past the range, ignored): a load per 64-tile step would
+    // put a full memory latency in front of each step, twice
+    uint32_t key[kIters];
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+        const int i = lo + it * 64 + lane;
+        const int ic = min(i, T - 1);
+        const uint32_t len = ranges[2 * ic + 1] - ranges[2 * ic];
+        key[it] = i < hi ? 255u - min(len >> 4, 255u) : 0u;
     }
     __syncthreads();
-    // exclusive prefix over keys of the totals, then over waves within a key
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+        if (lo + it * 64 >= hi) break;  // uniform across the wavefront
+        const bool ok = lo + it * 64 + lane < hi;
+        const uint64_t m = same_key_lanes(key[it], __ballot(ok));
+        if (ok && (m & lt) == 0) cnt[w][key[it]] += (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    // exclusive prefix over keys of the totals (four wavefront scans), then
+    // over waves within a key
+    uint32_t s = 0, incl = 0;
     if (t < 256) {
-        uint32_t s = 0;
 #pragma unroll
         for (int v = 0; v < kOrderWaves; ++v) s += cnt[v][t];
-        tot[t] = s;
+        incl = wave_incl_scan(s, lane);
+        if (lane == 63) ws[w] = incl;
     }
     __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-        uint32_t v = 0;
-        if (t < 256 && t >= d) v = tot[t - d];
-        __syncthreads();
-        if (t < 256) tot[t] += v;
-        __syncthreads();
-    }
     if (t < 256) {
-        uint32_t s = t > 0 ? tot[t - 1] : 0u;  // tiles with a smaller key
+        uint32_t pre = incl - s;  // tiles with a smaller key
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pre += k < w ? ws[k] : 0u;
 #pragma unroll
         for (int v = 0; v < kOrderWaves; ++v) {
             const uint32_t c = cnt[v][t];
-            cnt[v][t] = s;
-            s += c;
+            cnt[v][t] = pre;
+            pre += c;
         }
     }
     __syncthreads();
-    for (int i0 = lo; i0 < hi; i0 += 64) {
-        const int i = i0 + lane;
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+        if (lo + it * 64 >= hi) break;
+        const int i = lo + it * 64 + lane;
         const bool ok = i < hi;
-        const uint32_t key = ok ? key_of(i) : 0u;
-        const uint64_t m = same_key_lanes(key, __ballot(ok));
-        const uint32_t base = ok ? cnt[w][key] : 0u;
+        const uint64_t m = same_key_lanes(key[it], __ballot(ok));
+        const uint32_t base = ok ? cnt[w][key[it]] : 0u;
         const uint32_t pos = base + (uint32_t)__popcll(m & lt);
         if (ok && pos < (uint32_t)T) order[pos] = (uint32_t)i;
         // every lane has read its base before the group leader advances it
-        if (ok && (m & lt) == 0) cnt[w][key] = base + (uint32_t)__popcll(m);
+        if (ok && (m & lt) == 0) cnt[w][key[it]] = base + (uint32_t)__popcll(m);
     }
 }
 
@@ -249,7 +255,7 @@ extern "C" xgs_status xgs_tile_sort(const xgs_projected* p, const xgs_camera* ca
     }
     if ((s = radix_sort(k0, v0, k1, v1, b->num_instances, cap, bits, w.hist, st))) return s;
     if ((s = segment_ranges(b->keys, b->num_instances, cap, 32, b->ranges, st))) return s;
-    if (b->tile_order) {
+    if (b->tile_order && tiles > 0) {
         if (tiles <= kOrderMax)
             hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, st, b->ranges, (int)tiles, b->tile_order);
         else

@@ -172,6 +172,31 @@ def test_tile_sort_above_order_table_limit(xgs):
     check_sort(xgs, pr, cam, n)
 
 
+@pytest.mark.parametrize("size", [(2048, 2048), (2030, 2040)])
+def test_tile_sort_order_table_at_its_limit(xgs, size):
+    """16,384 and 16,256 tiles: each of the order kernel's 16 wavefronts
+    ranks 1,024 (1,016, the last step ragged) tiles; large rectangles crowded
+    towards one corner spread the list lengths over 8-10 buckets."""
+    rng = np.random.default_rng(8)
+    w_px, h_px = size
+    cam = synth.Camera(width=w_px, height=h_px, fx=900.0, fy=900.0, cx=w_px / 2, cy=h_px / 2)
+    hs, ws, ty, tx = oracle.grid_info(cam)
+    assert 16_000 < tx * ty <= 16384
+    n = 30_000
+    big = rng.random(n) < 0.03
+    x0 = np.where(big, (tx * rng.random(n) ** 3).astype(np.int64), rng.integers(0, tx, n))
+    y0 = np.where(big, (ty * rng.random(n) ** 3).astype(np.int64), rng.integers(0, ty, n))
+    w = np.where(big, rng.integers(1, 41, n), rng.integers(1, 4, n))
+    h = np.where(big, rng.integers(1, 41, n), rng.integers(1, 4, n))
+    x1 = np.minimum(x0 + w, tx); y1 = np.minimum(y0 + h, ty)
+    rect = np.stack([x0, y0, x1, y1], 1).astype(np.int32)
+    depth = rng.uniform(0.5, 9.0, n)
+    pr = oracle.Projection(None, None, depth, None, None, rect, ((x1 - x0) * (y1 - y0)).astype(np.int64),
+                           np.ones(n, np.int32))
+    m = check_sort(xgs, pr, cam, n)
+    assert m > 200_000
+
+
 def test_tile_sort_empty_and_overflow(xgs):
     cam = synth.tiny_camera()
     c = xgs.camera_from(cam)
