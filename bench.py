@@ -568,22 +568,29 @@ def serving(xgs, synth, dev, n_requests):
     srv.completed.clear()
 
     def poisson_run(qps, n, seed):
+        """Completion rate and the rate the sample's own arrivals offered."""
+        reqs = mk(n)
         t0 = time.perf_counter()
-        futs = poisson_load(srv, mk(n), qps, seed=seed, discard=True)
+        futs = poisson_load(srv, reqs, qps, seed=seed, discard=True)
+        t_arrived = time.perf_counter()
         for f in futs:
             f.result()
-        return n / (time.perf_counter() - t0)
+        return n / (time.perf_counter() - t0), n / (t_arrived - t0)
 
     # Sustained saturation: the highest Poisson arrival rate the server keeps
-    # up with (achieved >= 97% of offered), by bisection between 30% and 100%
-    # of the burst rate (1,000 requests per probe).  Burst batches are full,
-    # Poisson batches smaller, so the sustained rate is the lower one.
+    # up with, by bisection between 30% and 100% of the burst rate (1,000
+    # requests per probe).  A probe keeps up when its requests complete at
+    # >= 97% of the rate at which that probe's arrivals came in: a 1,000-
+    # arrival Poisson sample itself runs ~3% (one sigma) off its nominal rate,
+    # so a bar against the nominal rate would fail or pass some seeds whatever
+    # the server does.  Burst batches are full, Poisson batches smaller, so the
+    # sustained rate is the lower one.
     lo, hi = 0.3 * sat, sat
     for it in range(5):
         mid = 0.5 * (lo + hi)
-        got = poisson_run(mid, 1000, 60 + it)
+        got, offered = poisson_run(mid, 1000, 60 + it)
         srv.completed.clear()
-        if got >= 0.97 * mid:
+        if got >= 0.97 * offered:
             lo = mid
         else:
             hi = mid
@@ -594,8 +601,9 @@ def serving(xgs, synth, dev, n_requests):
         qps = frac * sustained
         log(f"serving: Poisson run at {frac:.0%} of the sustained rate = {qps:.0f} req/s")
         c0 = (srv.batches, srv.batched_requests, srv.graphs_captured, srv.overflows)
+        reqs = mk(n_requests)
         t0 = time.perf_counter()
-        futs = poisson_load(srv, mk(n_requests), qps, seed=seed, discard=True)
+        futs = poisson_load(srv, reqs, qps, seed=seed, discard=True)
         for f in futs:
             f.result()
         wall = time.perf_counter() - t0
@@ -618,6 +626,8 @@ def serving(xgs, synth, dev, n_requests):
             "resolutions": "320x240 / 640x480 / 1200x680 uniform", "requests": n_requests, "warmup_requests": 200,
             "saturation_frames_per_s": round(sat, 1), "saturation_mean_batch": round(sat_batch, 2),
             "sustained_poisson_req_per_s": round(sustained, 1),
+            "sustained_criterion": "highest nominal Poisson rate (bisection, 5 probes of 1,000 requests) whose "
+                                   "requests complete at >= 97% of the probe's own arrival rate",
             "load_reference": "load points are fractions of the sustained Poisson rate",
             "load_points": points, "p99_ms_at_80pct": points[-1]["p99_ms"], "peak_hbm_MB": round(peak, 1),
             "hbm_budget_MB": 4096, "capacity_overflows": overflows, "arena_growths": growths, "max_slots": 8,
