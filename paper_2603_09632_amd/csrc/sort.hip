@@ -302,8 +302,8 @@ __global__ void __launch_bounds__(256) radix_scan_kernel(uint32_t* __restrict__ 
 
 // Stable scatter.  Wavefront w of the block owns the contiguous run of
 // kSortRounds * 64 items that starts at base + w * kSortRounds * 64, so the
-// block order of equal digits is (wave, round, lane) and the waves only meet
-// twice.  Each wave first ranks every one of its items among the equal digits
+// block order of equal digits is (wave, round, lane) and the waves meet at
+// three barriers only (one of them for the digit bases).  Each wave first ranks every one of its items among the equal digits
 // of its round (the lanes whose digit ballots agree) and counts its digits into
 // its own LDS row; one barrier later thread t turns digit t's four wave
 // counts into the wave bases (the digit's global base from the totals and the
