@@ -172,6 +172,22 @@ def test_tile_sort_above_order_table_limit(xgs):
     check_sort(xgs, pr, cam, n)
 
 
+@pytest.mark.parametrize("m", [1, 63, 64, 2048, 4097])
+def test_tile_sort_block_and_wave_boundaries(xgs, m):
+    """Instance counts at the radix scatter's boundaries: a lone key, a
+    partial and a full first wavefront, one full 2,048-key block, and a block
+    more by one key (the last block's later wavefronts hold nothing); every
+    Gaussian touches one tile, depths with exact ties."""
+    rng = np.random.default_rng(9 + m)
+    cam = synth.Camera(width=640, height=480, fx=500.0, fy=500.0, cx=320.0, cy=240.0)
+    hs, ws, ty, tx = oracle.grid_info(cam)
+    x0 = rng.integers(0, tx, m); y0 = rng.integers(0, ty, m)
+    rect = np.stack([x0, y0, x0 + 1, y0 + 1], 1).astype(np.int32)
+    depth = rng.choice(np.linspace(0.5, 9.0, 40), m)
+    pr = oracle.Projection(None, None, depth, None, None, rect, np.ones(m, np.int64), np.ones(m, np.int32))
+    assert check_sort(xgs, pr, cam, m, extra_cap=3000) == m
+
+
 @pytest.mark.parametrize("size", [(2048, 2048), (2030, 2040)])
 def test_tile_sort_order_table_at_its_limit(xgs, size):
     """16,384 and 16,256 tiles: each of the order kernel's 16 wavefronts
