@@ -122,7 +122,11 @@ static int tile_bits(int64_t tiles) {
 constexpr int kOrderMax = 16384;
 constexpr int kOrderWaves = 16;
 
+// For a lane in `valid`: the lanes of `valid` whose key equals its own.
 __device__ __forceinline__ uint64_t same_key_lanes(uint32_t key, uint64_t valid) {
+    // one key across the valid lanes (runs of empty tiles): no bit ballots
+    const uint32_t k0 = __builtin_amdgcn_readlane(key, valid ? __builtin_ctzll(valid) : 0);
+    if (__ballot(((valid >> __lane_id()) & 1ull) && key != k0) == 0ull) return valid;
     uint64_t m = valid;
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
