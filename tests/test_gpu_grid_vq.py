@@ -45,6 +45,9 @@ def test_grid_sample(xgs, H, W, Hf, Wf, D, stride, oy, ox):
     (96, 128, 7, 9, 13, 3, 0),           # ragged grids (H_s W_s not a multiple of 4)
     (50, 70, 13, 5, 6, 4, 1),            # nearest, padded rows and columns
     (17, 1, 4, 1, 3, 2, 0),              # degenerate width
+    (33, 41, 5, 6, 3, 1, 0),             # stride 1: the one offset is the plain call
+    (40, 56, 6, 7, 2, 8, 1),             # 64 offsets, nearest
+    (5, 70, 3, 9, 2, 8, 0),              # H < stride: offsets past the last row are all padding
 ])
 def test_grid_sample_all_offsets(xgs, H, W, Hf, Wf, D, stride, mode):
     """Every offset's grid in one launch is bitwise the per-offset call, and
