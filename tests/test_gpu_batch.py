@@ -51,6 +51,34 @@ def test_batch_equals_each_request_alone(xgs):
             np.testing.assert_array_equal(np_(a), np_(r), err_msg=f"request {k}")
 
 
+def test_eight_slot_batch_equals_each_request_alone(xgs):
+    """Eight requests (three scenes, the three serving resolutions, two grid
+    strides) in one batch: a 75 x 179 virtual grid whose narrower slots leave
+    runs of empty tiles (the order kernel's one-key steps); every request
+    bitwise as rendered alone."""
+    poses = synth.room_trajectory(100, seed=10)
+    rooms = [synth.room_scene(n, seed=50 + k, c_sem=16) for k, n in enumerate((60_000, 150_000, 300_000))]
+    gs = [gaussians(s, xgs) for s in rooms]
+    res = [(320, 240, 262.5), (640, 480, 525.0), (1200, 680, 600.0)]
+    reqs = []
+    for k in range(8):
+        w, h, f = res[k % 3]
+        cam = synth.room_camera(w, h, f, poses[(11 * k + 3) % 100])
+        if k in (2, 5):
+            cam = cam.with_grid(2, k % 2, 1)
+        reqs.append((gs[k % 3], cam))
+    print(f"batch of {len(reqs)} requests", flush=True)
+    outs, b = xgs.render_batch(reqs, tiles_x=75)
+    torch.cuda.synchronize()
+    assert int(np_(b.status)[0]) == 0
+    assert int(b.ranges.shape[0]) == 75 * 179
+    for k, (g, cam) in enumerate(reqs):
+        ref = alone(xgs, g, cam)
+        torch.cuda.synchronize()
+        for a, r in zip(outs[k], ref):
+            np.testing.assert_array_equal(np_(a), np_(r), err_msg=f"request {k}")
+
+
 def test_batch_with_an_empty_slot_and_unused_capacity(xgs):
     s = synth.tiny_scene(seed=0, n=2000)
     g = gaussians(s, xgs)
