@@ -184,7 +184,7 @@ xgs_status xgs_tile_sort(const xgs_projected* p, const xgs_camera* cam, int64_t 
  * or pass a workspace (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same arguments, results and errors as
  * xgs_tile_sort, without ws: the sort runs in a scratch array of
- * xgs_tile_sort_noalloc_max_bytes() bytes (64 MiB: n = 2M Gaussians with
+ * xgs_tile_sort_noalloc_max_bytes() bytes (68 MiB: n = 2M Gaussians with
  * max_instances = 4M fit) that the library holds on each GPU it runs on until
  * the process ends.  A call whose xgs_tile_sort_workspace(n, max_instances,
  * tiles) exceeds that size returns XGS_ERR_CAPACITY before any launch.  The

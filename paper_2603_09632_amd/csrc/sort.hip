@@ -227,17 +227,20 @@ xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint
 // hold keys take part (the others return at once and their histogram columns
 // are never read), so the cost follows the instance count.
 //
-// Per block: digit histogram of its kSortItems keys, written digit-major
-// (hist[d * nb + b], nb = the grid size).
+// Per block: digit histogram of its kSortItems keys (BINS digits), written
+// digit-major (hist[d * nb + b], nb = the grid size).
+template <int BINS>
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t* __restrict__ keys,
                                                                  const int64_t* __restrict__ count,
                                                                  int shift, uint32_t mask,
                                                                  uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[256];
+    constexpr int DPT = BINS / kSortThreads;  // digits per thread
+    __shared__ uint32_t h[BINS];
     const int64_t m = *count;
     const int64_t base = (int64_t)blockIdx.x * kSortItems;
     if (base >= m) return;  // uniform: a column no scan reads
-    h[threadIdx.x] = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) h[threadIdx.x + kSortThreads * j] = 0;
     // all of the block's keys are loaded before any is counted (a load per
     // count would wait a full memory latency each)
     uint64_t k[kSortRounds];
@@ -253,7 +256,11 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t
         if (i < m) atomicAdd(&h[(uint32_t)(k[r] >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = threadIdx.x + kSortThreads * j;
+        hist[(int64_t)d * gridDim.x + blockIdx.x] = h[d];
+    }
 }
 
 // One workgroup per digit d: exclusive scan of d's per-block counts in place
@@ -300,26 +307,30 @@ __global__ void __launch_bounds__(256) radix_scan_kernel(uint32_t* __restrict__ 
     if (t == 0) totals[d] = carry;
 }
 
-// Stable scatter.  Wavefront w of the block owns the contiguous run of
-// kSortRounds * 64 items that starts at base + w * kSortRounds * 64, so the
-// block order of equal digits is (wave, round, lane) and the waves meet at
-// three barriers only (one of them for the digit bases).  Each wave first ranks every one of its items among the equal digits
-// of its round (the lanes whose digit ballots agree) and counts its digits into
-// its own LDS row; one barrier later thread t turns digit t's four wave
-// counts into the wave bases (the digit's global base from the totals and the
-// block's offset from the scanned histogram, plus the counts of the earlier
-// waves); a second barrier later every wave walks its rounds again in order,
-// each item going to its wave base plus its rank, the digit's first lane
-// moving that base on by the round's count.  LDS operations of one wave
-// complete in issue order, so a wave's own counter row needs no barrier.
+// Stable scatter of BINS digits.  Wavefront w of the block owns the
+// contiguous run of kSortRounds * 64 items that starts at base + w *
+// kSortRounds * 64, so the block order of equal digits is (wave, round, lane)
+// and the waves meet at a few barriers only (the digit bases, then two).
+// Each wave first ranks every one of its items among the equal digits of its
+// round (the lanes whose digit ballots agree) and counts its digits into its
+// own LDS row; one barrier later thread t turns the four wave counts of each
+// of its digits (t, t + 256, ...) into the wave bases (the digit's global
+// base from the totals and the block's offset from the scanned histogram,
+// plus the counts of the earlier waves); a second barrier later every wave
+// walks its rounds again in order, each item going to its wave base plus its
+// rank, the digit's first lane moving that base on by the round's count.  LDS
+// operations of one wave complete in issue order, so a wave's own counter row
+// needs no barrier.
+template <int BINS>
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const int64_t* __restrict__ count, int shift, uint32_t mask,
     int nbits, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals) {
     constexpr int kWaves = kSortThreads / 64;
+    constexpr int DPT = BINS / kSortThreads;  // digits per thread
     static_assert(kWaves == 4 && kSortRounds * 64 * kWaves == kSortItems, "four wavefronts per sort block");
-    __shared__ uint32_t run[kWaves][256];
-    __shared__ uint32_t ws[kWaves];
+    __shared__ uint32_t run[kWaves][BINS];
+    __shared__ uint32_t ws[DPT][kWaves];
     const int64_t m = *count;
     const int64_t base = (int64_t)blockIdx.x * kSortItems;
     if (base >= m) return;
@@ -335,21 +346,38 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
         rkey[r] = i < m ? kin[i] : 0ull;
         rval[r] = i < m ? vin[i] : 0u;
     }
-    // digit t's base for this block: exclusive prefix of the digit totals
-    // plus the block's offset among the keys with digit t
-    uint32_t g;
+    // digit d's base for this block (d = t + 256 j): exclusive prefix of the
+    // digit totals plus the block's offset among the keys with digit d
+    uint32_t g[DPT];
     {
-        const uint32_t tv = totals[t];
-        const uint32_t incl = wave_incl_scan(tv, lane);
-        if (lane == 63) ws[w] = incl;
-        __syncthreads();
-        uint32_t pre = 0;
+        uint32_t tv[DPT], hv[DPT], incl[DPT];
 #pragma unroll
-        for (int k = 0; k < kWaves; ++k) pre += k < w ? ws[k] : 0u;
-        g = pre + incl - tv + hist[(int64_t)t * gridDim.x + blockIdx.x];
+        for (int j = 0; j < DPT; ++j) {
+            tv[j] = totals[t + kSortThreads * j];
+            hv[j] = hist[(int64_t)(t + kSortThreads * j) * gridDim.x + blockIdx.x];
+        }
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            incl[j] = wave_incl_scan(tv[j], lane);
+            if (lane == 63) ws[j][w] = incl[j];
+        }
+        __syncthreads();
+        uint32_t carry = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            uint32_t pre = 0, tot = 0;
+#pragma unroll
+            for (int k = 0; k < kWaves; ++k) {
+                const uint32_t x = ws[j][k];
+                pre += k < w ? x : 0u;
+                tot += x;
+            }
+            g[j] = carry + pre + incl[j] - tv[j] + hv[j];
+            carry += tot;
+        }
     }
 #pragma unroll
-    for (int k = 0; k < 256 / 64; ++k) run[w][lane + 64 * k] = 0u;
+    for (int k = 0; k < BINS / 64; ++k) run[w][lane + 64 * k] = 0u;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     // rank among the round's equal digits (bits 0-7) and, for the digit's
     // first lane, the round's count of that digit (bits 8-15)
@@ -368,12 +396,14 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
         if (valid && rank == 0) atomicAdd(&run[w][d], cnt);
     }
     __syncthreads();
-    {
-        const uint32_t c0 = run[0][t], c1 = run[1][t], c2 = run[2][t];
-        run[0][t] = g;
-        run[1][t] = g + c0;
-        run[2][t] = g + c0 + c1;
-        run[3][t] = g + c0 + c1 + c2;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = t + kSortThreads * j;
+        const uint32_t c0 = run[0][d], c1 = run[1][d], c2 = run[2][d];
+        run[0][d] = g[j];
+        run[1][d] = g[j] + c0;
+        run[2][d] = g[j] + c0 + c1;
+        run[3][d] = g[j] + c0 + c1 + c2;
     }
     __syncthreads();
 #pragma unroll
@@ -389,24 +419,38 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     }
 }
 
-int radix_passes(int key_bits) { return (key_bits + 7) / 8; }
+int radix_digit_bits(int key_bits, int64_t cap) {
+    return (key_bits + 8) / 9 < (key_bits + 7) / 8 && sort_blocks(cap) <= kRadix9MaxBlocks ? 9 : 8;
+}
+int radix_passes(int key_bits, int64_t cap) {
+    const int db = radix_digit_bits(key_bits, cap);
+    return (key_bits + db - 1) / db;
+}
+
+template <int BINS>
+static void radix_pass(const uint64_t* ki, const uint32_t* vi, uint64_t* ko, uint32_t* vo, const int64_t* count,
+                       int64_t nb, int shift, int nbits, uint32_t* hist, hipStream_t stream) {
+    const uint32_t mask = (1u << nbits) - 1u;
+    uint32_t* totals = hist + (int64_t)BINS * nb;
+    hipLaunchKernelGGL(radix_hist_kernel<BINS>, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, ki, count, shift,
+                       mask, hist);
+    hipLaunchKernelGGL(radix_scan_kernel, dim3(BINS), dim3(256), 0, stream, hist, totals, nb, count);
+    hipLaunchKernelGGL(radix_scatter_kernel<BINS>, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, ki, vi, ko, vo,
+                       count, shift, mask, nbits, hist, totals);
+}
 
 xgs_status radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const int64_t* count,
                       int64_t cap, int key_bits, uint32_t* hist, hipStream_t stream) {
     int64_t nb = sort_blocks(cap);
     if (nb == 0) return XGS_OK;
-    int passes = radix_passes(key_bits);
-    uint32_t* totals = hist + 256 * nb;
+    const int db = radix_digit_bits(key_bits, cap);
+    const int passes = radix_passes(key_bits, cap);
     uint64_t* ki = k0; uint32_t* vi = v0; uint64_t* ko = k1; uint32_t* vo = v1;
     for (int p = 0; p < passes; ++p) {
-        int shift = 8 * p;
-        int nbits = key_bits - shift < 8 ? key_bits - shift : 8;
-        uint32_t mask = (1u << nbits) - 1u;
-        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, ki,
-                           count, shift, mask, hist);
-        hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(256), 0, stream, hist, totals, nb, count);
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kSortThreads), 0, stream,
-                           ki, vi, ko, vo, count, shift, mask, nbits, hist, totals);
+        const int shift = db * p;
+        const int nbits = key_bits - shift < db ? key_bits - shift : db;
+        if (db == 9) radix_pass<512>(ki, vi, ko, vo, count, nb, shift, nbits, hist, stream);
+        else radix_pass<256>(ki, vi, ko, vo, count, nb, shift, nbits, hist, stream);
         uint64_t* tk = ki; ki = ko; ko = tk;
         uint32_t* tv = vi; vi = vo; vo = tv;
     }

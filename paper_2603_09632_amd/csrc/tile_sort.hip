@@ -13,7 +13,7 @@ namespace xgs {
 // for the sort, one copy per GPU (each device that runs the entry point holds
 // it until the process ends).  In host code the name is a host-side stand-in:
 // its device address comes from hipGetSymbolAddress, once per device.
-constexpr size_t kSortScratchBytes = size_t(64) << 20;
+constexpr size_t kSortScratchBytes = size_t(68) << 20;
 static __device__ __align__(256) unsigned char scratch[kSortScratchBytes];
 constexpr int kMaxScratchDevices = 64;
 static void* g_scratch_ptr[kMaxScratchDevices];
@@ -98,7 +98,7 @@ static SortWs carve_sort(void* base, int64_t n, int64_t cap, size_t* bytes) {
     w.partials = c.take<uint64_t>(scan_blocks(n) + 1);
     w.keys_alt = c.take<uint64_t>(cap > 0 ? cap : 1);
     w.vals_alt = c.take<uint32_t>(cap > 0 ? cap : 1);
-    w.hist = c.take<uint32_t>(radix_hist_words(cap, 64));
+    w.hist = c.take<uint32_t>(radix_hist_words(cap));
     w.total = c.take<int64_t>(1);
     *bytes = c.total();
     return w;
@@ -246,7 +246,7 @@ extern "C" xgs_status xgs_tile_sort(const xgs_projected* p, const xgs_camera* ca
                                       b->status, b->ranges, 2 * tiles, st);
     if (s) return s;
     int bits = 32 + tile_bits(tiles);
-    bool even = radix_passes(bits) % 2 == 0;
+    bool even = radix_passes(bits, cap) % 2 == 0;
     uint64_t* k0 = even ? b->keys : w.keys_alt;
     uint32_t* v0 = even ? b->vals : w.vals_alt;
     uint64_t* k1 = even ? w.keys_alt : b->keys;

@@ -1338,7 +1338,7 @@ static EmaWs carve_ema(void* base, int64_t N, int D, int K, size_t* bytes) {
     w.vals = c.take<uint32_t>(n1);
     w.keys_alt = c.take<uint64_t>(n1);
     w.vals_alt = c.take<uint32_t>(n1);
-    w.hist = c.take<uint32_t>(radix_hist_words(n1, 64));
+    w.hist = c.take<uint32_t>(radix_hist_words(n1));
     w.ranges = c.take<uint32_t>(2 * (size_t)(K > 0 ? K + 1 : 2));
     w.count = c.take<int64_t>(1);
     w.total = c.take<float>(1);
@@ -1544,7 +1544,7 @@ static xgs_status ema_impl(const char* who, const float* X, const int32_t* idx, 
     if ((s = check_launch(who))) return s;
     const int bits = bits_for((int64_t)K + 1);
     if ((s = radix_sort(w.keys, w.vals, w.keys_alt, w.vals_alt, w.count, N, bits, w.hist, st))) return s;
-    const bool even = radix_passes(bits) % 2 == 0;
+    const bool even = radix_passes(bits, N) % 2 == 0;
     const uint64_t* sk = even ? w.keys : w.keys_alt;
     const uint32_t* sv = even ? w.vals : w.vals_alt;
     if ((s = segment_ranges(sk, w.count, N, 0, w.ranges, st))) return s;

@@ -111,9 +111,12 @@ def test_tile_sort_bitexact_tiny(xgs, stride):
     check_sort(xgs, oracle.project(scene, cam), cam, scene.n, extra_cap=777)
 
 
-def test_tile_sort_bitexact_room(xgs, room300k):
+@pytest.mark.parametrize("extra_cap", [0, 1_600_000])
+def test_tile_sort_bitexact_room(xgs, room300k, extra_cap):
+    """43-bit keys: five 9-bit radix passes at the exact capacity, six 8-bit
+    passes when the capacity needs more than 768 sort blocks; both bit-exact."""
     cam = room_cam()
-    m = check_sort(xgs, oracle.project(room300k, cam), cam, room300k.n)
+    m = check_sort(xgs, oracle.project(room300k, cam), cam, room300k.n, extra_cap=extra_cap)
     assert m > 100_000  # spans many sort blocks and all tile bits
 
 

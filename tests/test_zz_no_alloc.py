@@ -61,7 +61,8 @@ def test_noalloc_tile_sort_rejects_sizes_beyond_its_scratch(xgs):
     rejected as invalid arguments, so the status shows which check fired)."""
     lib = xgs.lib
     cap = int(lib.xgs_tile_sort_noalloc_max_bytes())
-    assert cap == 64 << 20
+    assert cap == 68 << 20
+    assert lib.xgs_tile_sort_workspace(2_000_000, 4_000_000, 3225) <= cap  # the documented fit
     cam = xgs.camera_from(synth.room_camera(1200, 680, 600.0, synth.room_trajectory(100, seed=10)[0]))
     n, m = 2_000_000, 8_000_000
     assert lib.xgs_tile_sort_workspace(n, m, 3225) > cap
