@@ -31,6 +31,16 @@ xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint
                               int64_t* total, int64_t cap, int64_t* count, int32_t* status,
                               uint32_t* zero_p, int64_t zero_n, hipStream_t stream);
 
+// Up to this many scan blocks the apply pass sums the block totals before
+// its own block itself (no separate partials pass).
+constexpr int64_t kFusedScanBlocks = 4096;
+
+// The first pass of exclusive_scan_u32 alone: partials[b] = the sum of block
+// b (kScanItems values), zero_p[0..zero_n) cleared by the same launch; for a
+// caller that applies the prefix itself.
+xgs_status scan_block_totals(const uint32_t* in, int64_t n, uint64_t* partials, uint32_t* zero_p, int64_t zero_n,
+                             hipStream_t stream);
+
 // Stable LSD radix sort of the first *count pairs (count <= cap) on key bits
 // [0, key_bits), in passes of radix_digit_bits(key_bits, cap) bits: 9 when
 // that takes fewer passes than 8 (5 instead of 6 at 41-45 bits) and cap needs

@@ -152,7 +152,6 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(const uint32_t* __restr
 // Apply without the separate partials pass: block b sums the block totals
 // partials[0..b) itself (nb <= kFusedScanBlocks keeps that cheap), and the
 // last block writes the total, count and status as scan_partials_kernel does.
-constexpr int64_t kFusedScanBlocks = 4096;
 
 __global__ void __launch_bounds__(256) scan_apply_fused_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                               const uint64_t* __restrict__ partials, int64_t nb,
@@ -196,6 +195,14 @@ __global__ void __launch_bounds__(256) scan_apply_fused_kernel(const uint32_t* _
             *status = tot > (uint64_t)cap ? 1 : 0;
         }
     }
+}
+
+xgs_status scan_block_totals(const uint32_t* in, int64_t n, uint64_t* partials, uint32_t* zero_p, int64_t zero_n,
+                             hipStream_t stream) {
+    const int64_t nb = scan_blocks(n);
+    if (nb <= 0) return XGS_OK;
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, stream, in, n, partials, zero_p, zero_n);
+    return check_launch("scan_block_totals");
 }
 
 xgs_status exclusive_scan_u32(const uint32_t* in, int64_t n, uint64_t* out, uint64_t* partials,

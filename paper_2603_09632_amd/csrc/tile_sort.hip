@@ -26,6 +26,57 @@ static std::mutex g_scratch_mu;
 // the tile as the row-major index within its rectangle.  Each store
 // instruction then covers 64 consecutive keys.  Positions at or beyond cap
 // are not written (on overflow the sort sees zero instances anyway).
+//
+// emit_wave: the wavefront's part, given the run's first position `base`,
+// the lane's count and its inclusive prefix over the wavefront.
+__device__ __forceinline__ void emit_wave(int64_t n, int64_t i0, uint64_t base, uint32_t cnt, uint32_t incl,
+                                          uint32_t total, const uint2* __restrict__ tile_rect,
+                                          const float4* __restrict__ splat, int64_t cap, int tiles_x,
+                                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                          uint32_t* s_excl, uint2* s_rect, uint32_t* s_dbits) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = i0 + lane;
+    uint2 r = make_uint2(0u, 0u);
+    uint32_t dbits = 0;
+    if (i < n && cnt > 0) {
+        r = tile_rect[i];
+        dbits = __float_as_uint(splat[2 * i + 1].z);
+    }
+    s_excl[lane] = incl - cnt;
+    s_rect[lane] = r;
+    s_dbits[lane] = dbits;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint32_t t = lane; t < total; t += 64) {
+        const uint64_t pos = base + t;
+        if (pos >= (uint64_t)cap) break;  // positions only grow along the loop
+        // owner: the last lane whose exclusive start is <= t (lanes with no
+        // instances share their start with the next lane and are skipped)
+        int lo = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1)
+            if (lo + step < 64 && s_excl[lo + step] <= t) lo += step;
+        const uint32_t local = t - s_excl[lo];
+        const uint2 rr = s_rect[lo];
+        const uint32_t x0 = rr.x & 0xFFFFu, y0 = rr.x >> 16, x1 = rr.y & 0xFFFFu;
+        const uint32_t wd = x1 - x0;
+        const uint32_t y = y0 + local / wd, x = x0 + local - (local / wd) * wd;
+        const uint64_t tile = (uint64_t)y * (uint32_t)tiles_x + x;
+        keys[pos] = (tile << 32) | s_dbits[lo];
+        vals[pos] = (uint32_t)(i0 + lo);
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan_counts(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Emission after a full exclusive scan of the counts (offsets).
 __global__ void __launch_bounds__(256) emit_keys_kernel(
     int64_t n, const uint2* __restrict__ tile_rect, const uint32_t* __restrict__ touched,
     const float4* __restrict__ splat, const uint64_t* __restrict__ offsets, int64_t cap, int tiles_x,
@@ -38,48 +89,74 @@ __global__ void __launch_bounds__(256) emit_keys_kernel(
     if (i0 >= n) return;  // uniform per wave
     const int64_t i = i0 + lane;
     const uint64_t base = offsets[i0];  // issued with the count load
-    uint32_t cnt = 0;
-    uint2 r = make_uint2(0u, 0u);
-    uint32_t dbits = 0;
-    if (i < n) {
-        cnt = touched[i];
-        if (cnt > 0) {
-            r = tile_rect[i];
-            dbits = __float_as_uint(splat[2 * i + 1].z);
-        }
-    }
-    // inclusive prefix of the counts over the wave
-    uint32_t incl = cnt;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += o;
-    }
+    const uint32_t cnt = i < n ? touched[i] : 0u;
+    const uint32_t incl = wave_incl_scan_counts(cnt, lane);
     const uint32_t total = __shfl(incl, 63, 64);
     if (total == 0) return;  // uniform
-    s_excl[w][lane] = incl - cnt;
-    s_rect[w][lane] = r;
-    s_dbits[w][lane] = dbits;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (uint32_t t = lane; t < total; t += 64) {
-        const uint64_t pos = base + t;
-        if (pos >= (uint64_t)cap) break;  // positions only grow along the loop
-        // owner: the last lane whose exclusive start is <= t (lanes with no
-        // instances share their start with the next lane and are skipped)
-        int lo = 0;
+    emit_wave(n, i0, base, cnt, incl, total, tile_rect, splat, cap, tiles_x, keys, vals, s_excl[w], s_rect[w],
+              s_dbits[w]);
+}
+
+// Emission with the scan's apply pass folded in (no offsets array): given
+// the scan-block totals (partials[b], blocks of kScanItems counts),
+// workgroup k (256 Gaussians, part k % 8 of scan block k / 8) starts at the
+// totals of the scan blocks before its own plus the counts of the earlier
+// workgroups of its scan block, and each wavefront adds the counts of the
+// workgroup's earlier wavefronts.  The last workgroup writes the total, and
+// count / status as the scan does (count 0 and status 1 past cap).
+__global__ void __launch_bounds__(256) emit_scan_keys_kernel(
+    int64_t n, const uint2* __restrict__ tile_rect, const uint32_t* __restrict__ touched,
+    const float4* __restrict__ splat, const uint64_t* __restrict__ partials, int64_t cap, int tiles_x,
+    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t* __restrict__ total_out,
+    int64_t* __restrict__ count, int32_t* __restrict__ status) {
+    constexpr int SUB = kScanItems / 256;  // workgroups per scan block
+    __shared__ uint32_t s_excl[4][64];
+    __shared__ uint2 s_rect[4][64];
+    __shared__ uint32_t s_dbits[4][64];
+    __shared__ uint64_t red[4];
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t sb = (int64_t)blockIdx.x / SUB;
+    const int sub = (int)(blockIdx.x - sb * SUB);
+    const int64_t i0 = (int64_t)blockIdx.x * 256 + 64 * w;
+    const int64_t i = i0 + lane;
+    // the counts of the scan block's earlier workgroups (in bounds: below
+    // blockIdx.x * 256 < n; the others clamped and dropped) and the lane's own
+    uint32_t pc[SUB - 1];
 #pragma unroll
-        for (int step = 32; step >= 1; step >>= 1)
-            if (lo + step < 64 && s_excl[w][lo + step] <= t) lo += step;
-        const uint32_t local = t - s_excl[w][lo];
-        const uint2 rr = s_rect[w][lo];
-        const uint32_t x0 = rr.x & 0xFFFFu, y0 = rr.x >> 16, x1 = rr.y & 0xFFFFu;
-        const uint32_t wd = x1 - x0;
-        const uint32_t y = y0 + local / wd, x = x0 + local - (local / wd) * wd;
-        const uint64_t tile = (uint64_t)y * (uint32_t)tiles_x + x;
-        keys[pos] = (tile << 32) | s_dbits[w][lo];
-        vals[pos] = (uint32_t)(i0 + lo);
+    for (int c = 0; c < SUB - 1; ++c) {
+        const int64_t j = sb * kScanItems + c * 256 + t;
+        const uint32_t x = touched[j < n ? j : n - 1];
+        pc[c] = c < sub ? x : 0u;
     }
+    const uint32_t cnt = i < n ? touched[i] : 0u;
+    uint64_t acc = 0;
+    for (int64_t j = t; j < sb; j += 256) acc += partials[j];
+#pragma unroll
+    for (int c = 0; c < SUB - 1; ++c) acc += pc[c];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    const uint32_t incl = wave_incl_scan_counts(cnt, lane);
+    if (lane == 0) red[w] = acc;
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    const uint64_t block_base = (red[0] + red[1]) + (red[2] + red[3]);
+    uint64_t base = block_base;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) base += k < w ? (uint64_t)wsum[k] : 0ull;
+    if (blockIdx.x == gridDim.x - 1 && t == 0) {
+        const uint64_t tot = block_base + (uint64_t)wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        *total_out = (int64_t)tot;
+        if (cap >= 0) {
+            *count = (int64_t)(tot > (uint64_t)cap ? 0 : tot);
+            *status = tot > (uint64_t)cap ? 1 : 0;
+        }
+    }
+    if (i0 >= n) return;  // uniform per wave
+    const uint32_t total = __shfl(incl, 63, 64);
+    if (total == 0) return;  // uniform
+    emit_wave(n, i0, base, cnt, incl, total, tile_rect, splat, cap, tiles_x, keys, vals, s_excl[w], s_rect[w],
+              s_dbits[w]);
 }
 
 struct SortWs {
@@ -241,21 +318,33 @@ extern "C" xgs_status xgs_tile_sort(const xgs_projected* p, const xgs_camera* ca
     Grid g = grid_of(*cam);
     int64_t tiles = (int64_t)g.tx * g.ty;
     const int64_t cap = b->max_instances;
-    // the scan also clears the per-tile ranges (empty tiles keep (0, 0))
-    xgs_status s = exclusive_scan_u32(p->tiles_touched, n, w.offsets, w.partials, w.total, cap, b->num_instances,
-                                      b->status, b->ranges, 2 * tiles, st);
-    if (s) return s;
     int bits = 32 + tile_bits(tiles);
     bool even = radix_passes(bits, cap) % 2 == 0;
     uint64_t* k0 = even ? b->keys : w.keys_alt;
     uint32_t* v0 = even ? b->vals : w.vals_alt;
     uint64_t* k1 = even ? w.keys_alt : b->keys;
     uint32_t* v1 = even ? w.vals_alt : b->vals;
-    if (n > 0) {
-        hipLaunchKernelGGL(emit_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+    xgs_status s = XGS_OK;
+    if (n > 0 && scan_blocks(n) <= kFusedScanBlocks) {
+        // block totals (clearing the per-tile ranges: empty tiles keep (0, 0)),
+        // then the emission applies the prefix itself
+        if ((s = scan_block_totals(p->tiles_touched, n, w.partials, b->ranges, 2 * tiles, st))) return s;
+        hipLaunchKernelGGL(emit_scan_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
                            reinterpret_cast<const uint2*>(p->tile_rect), p->tiles_touched,
-                           reinterpret_cast<const float4*>(p->splat), w.offsets, cap, g.tx, k0, v0);
+                           reinterpret_cast<const float4*>(p->splat), w.partials, cap, g.tx, k0, v0, w.total,
+                           b->num_instances, b->status);
         if ((s = check_launch("xgs_tile_sort emit"))) return s;
+    } else {
+        // the scan also clears the per-tile ranges (empty tiles keep (0, 0))
+        if ((s = exclusive_scan_u32(p->tiles_touched, n, w.offsets, w.partials, w.total, cap, b->num_instances,
+                                    b->status, b->ranges, 2 * tiles, st)))
+            return s;
+        if (n > 0) {
+            hipLaunchKernelGGL(emit_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                               reinterpret_cast<const uint2*>(p->tile_rect), p->tiles_touched,
+                               reinterpret_cast<const float4*>(p->splat), w.offsets, cap, g.tx, k0, v0);
+            if ((s = check_launch("xgs_tile_sort emit"))) return s;
+        }
     }
     if ((s = radix_sort(k0, v0, k1, v1, b->num_instances, cap, bits, w.hist, st))) return s;
     if ((s = segment_ranges(b->keys, b->num_instances, cap, 32, b->ranges, st))) return s;
