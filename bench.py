@@ -8,10 +8,14 @@ One step = one pass of every hot-path row over one batch of synthetic input:
   a6-a7  BF16-MFMA VQ assignment (top-4 + FP32 rescore) of 816,000 x 768
          features against 4,096 codewords, then one EMA update.
 The headline value is fwd+bwd ms/frame (a1-a4, HIP events on the launch
-stream, mean over the timed steps); the backward's zeroing of its
-accumulated gradients is issued on a side stream at the start of the frame
-and overlaps the projection, sort and forward pass.  Everything is resident in HBM before the
-timed region; nothing is skipped inside it.
+stream, mean over the timed steps).  The backward's zeroing of its
+accumulated gradients (a call of its own) goes to a side stream that waits
+only for the previous frame's backward, so it runs beside the previous
+step's target and VQ stages and its own time falls outside the frame's
+events (held back to the frame's start instead, it runs beside the
+projection, sort and forward and the frame reads ~25 us more; the step time
+is the same either way).  Everything is resident in HBM before the timed
+region; nothing is skipped inside it.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
 """
@@ -142,8 +146,8 @@ def main():
              "vq_ema"]
     stream = torch.cuda.current_stream()
     # The backward's zeroing of the accumulated gradients runs on a side
-    # stream while the frame projects, sorts and composites forward (those
-    # leave HBM bandwidth idle); the backward waits for it.
+    # stream as soon as the previous frame's backward is done (beside that
+    # step's target and VQ stages); this frame's backward waits for it.
     side = torch.cuda.Stream(device=dev)
     bwd_done = torch.cuda.Event()
     bwd_done.record(stream)

@@ -57,7 +57,7 @@ __device__ __forceinline__ float sample(const float* __restrict__ Pd, int Wf, co
 }
 
 // channels per thread: the source coordinates of a pixel are computed once per chunk
-constexpr int kChanChunk = 32;
+constexpr int kChanChunk = 16;
 
 // ALL: blockIdx.z is the grid offset o = oy s + ox, whose grid goes to
 // G + o D Hs Ws and V + o Hs Ws (the oy, ox arguments are ignored).
