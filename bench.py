@@ -9,13 +9,9 @@ One step = one pass of every hot-path row over one batch of synthetic input:
          features against 4,096 codewords, then one EMA update.
 The headline value is fwd+bwd ms/frame (a1-a4, HIP events on the launch
 stream, mean over the timed steps).  The backward's zeroing of its
-accumulated gradients (a call of its own) goes to a side stream that waits
-only for the previous frame's backward, so it runs beside the previous
-step's target and VQ stages and its own time falls outside the frame's
-events (held back to the frame's start instead, it runs beside the
-projection, sort and forward and the frame reads ~25 us more; the step time
-is the same either way).  Everything is resident in HBM before the timed
-region; nothing is skipped inside it.
+accumulated gradients (a call of its own) runs on a side stream beside the
+forward pass, inside the frame's events.  Everything is resident in HBM
+before the timed region; nothing is skipped inside it.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
 """
@@ -146,28 +142,25 @@ def main():
              "vq_ema"]
     stream = torch.cuda.current_stream()
     # The backward's zeroing of the accumulated gradients runs on a side
-    # stream as soon as the previous frame's backward is done (beside that
-    # step's target and VQ stages); this frame's backward waits for it.
+    # stream beside this frame's forward pass (issued once the sort is done,
+    # so inside the frame's events); the backward waits for it.
     side = torch.cuda.Stream(device=dev)
-    bwd_done = torch.cuda.Event()
-    bwd_done.record(stream)
 
     def step(k, evs):
         c = cams[k]
         zeroed = torch.cuda.Event()
-        side.wait_event(bwd_done)
-        xgs.xgs_render_bwd_zero(g, grads, bwd_ws, stream=side)
-        zeroed.record(side)
         evs[0].record(stream)
         xgs.xgs_project(g, c, out=p)
         evs[1].record(stream)
         xgs.xgs_tile_sort(p, c, g.n, b)
         evs[2].record(stream)
+        side.wait_event(evs[2])
+        xgs.xgs_render_bwd_zero(g, grads, bwd_ws, stream=side)
+        zeroed.record(side)
         xgs.xgs_render_fwd(g, p, b, c, out=out, final_T=fT, n_last=nl)
         evs[3].record(stream)
         stream.wait_event(zeroed)
         xgs.xgs_render_bwd(g, p, b, c, d_out, fT, nl, flags=xgs.BWD_PREZEROED, grads=grads, workspace=bwd_ws)
-        bwd_done.record(stream)
         evs[4].record(stream)
         xgs.xgs_grid_sample(P, 480, 640, G=G, V=V)
         evs[5].record(stream)
